@@ -1,0 +1,197 @@
+/*
+ * libkdeplugin — PLUGIN bandwidth selection for univariate Gaussian kernel
+ * density estimation on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the two-stage plug-in selector of Section 3, Algorithm 1 of
+ * Gramacki, Sawerwain and Gramacki, "FPGA-Based Bandwidth Selection for Kernel
+ * Density Estimation Using High Level Synthesis Approach" (arXiv:1505.02100):
+ *
+ *   Step I    V = sum (X_i - mean)^2 / (n - 1),  sigma = sqrt(V)
+ *   Step II   Psi8 = 105 / (32 sqrt(pi) sigma^9)
+ *   Step III  g1 = (-2 K6(0) / (mu2 Psi8 n))^(1/9),      K6(0) = -15/sqrt(2 pi)
+ *   Step IV   Psi6(g1) = (n^2 g1^7)^-1 sum_i sum_j K6((X_i - X_j)/g1)
+ *   Step V    g2 = (-2 K4(0) / (mu2 Psi6 n))^(1/7),      K4(0) = 3/sqrt(2 pi)
+ *   Step VI   Psi4(g2) = (n^2 g2^5)^-1 sum_i sum_j K4((X_i - X_j)/g2)
+ *   Step VII  h = (R(K) / (mu2^2 Psi4 n))^(1/5),         R(K) = 1/(2 sqrt(pi)), mu2 = 1
+ *
+ * with K6(x) = (x^6 - 15x^4 + 45x^2 - 15) phi(x), K4(x) = (x^4 - 6x^2 + 3) phi(x)
+ * and phi the standard normal density (equation (2)).  The double sums are
+ * evaluated in the symmetric form of equations (6)-(7): twice the strict upper
+ * triangle i < j plus the diagonal n K(0), which is added analytically.
+ *
+ * Conventions for every entry point:
+ *  - Integer return values: KDE_OK (0) on success, a negative KDE_E* code on
+ *    failure.  Functions returning double return NaN on failure.  In both
+ *    cases kde_last_error() / kde_last_error_message() hold the reason
+ *    (thread-local).  No C++ exception crosses this interface.
+ *  - The caller owns every input and output buffer.  The library never keeps
+ *    a pointer to caller data after a synchronous call returns.
+ *  - Samples x are contiguous arrays of n values.  KDE_MEM_HOST means an
+ *    ordinary host pointer; KDE_MEM_DEVICE means a pointer to memory on the
+ *    context's GPU (for example a torch tensor's data_ptr()).
+ *  - A kde_stream is a hipStream_t passed as void*; NULL is the null stream.
+ *  - Every call on a context is synchronous with respect to the host unless
+ *    its comment says otherwise; work is enqueued on the given stream and the
+ *    call waits for that stream before returning.
+ *  - A context is not thread-safe: use one context per host thread.  The
+ *    literal calls kde_psi() and kde_plugin_bandwidth() use a process-wide
+ *    default context guarded by a mutex.
+ *  - Results are deterministic: the same samples give bitwise-identical
+ *    results on every call, alone or inside any batch, for a given context
+ *    configuration (precision and tile shape).
+ */
+#ifndef KDEPLUGIN_H
+#define KDEPLUGIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define KDE_OK 0
+#define KDE_EINVAL (-1)      /* null pointer, n < 2 (Step I divides by n-1), r not in {4,6},
+                                g not finite and positive, bad enum value               */
+#define KDE_ENONFINITE (-2)  /* NaN or Inf among the samples (or their sum overflows)     */
+#define KDE_EDEGENERATE (-3) /* sigma = 0 (constant sample: Psi8 of Step II is infinite),
+                                or Psi6 >= 0 / Psi4 <= 0, which exact arithmetic excludes
+                                (Psi6 < 0 < Psi4 for every sample), i.e. numerical failure */
+#define KDE_ENOMEM (-4)      /* device or host allocation failed, or over memory budget   */
+#define KDE_EDEVICE (-5)     /* HIP runtime error; the message names the call             */
+#define KDE_ETIMEOUT (-6)    /* an in-kernel wait for a previous stage exceeded its limit */
+#define KDE_EBUSY (-7)       /* server: request not finished yet / queue full             */
+
+/* ------------------------------------------------------------------ enums */
+#define KDE_FP64_PLAIN 0 /* pair sums in FP64 with the printed polynomials and FP64 exp      */
+#define KDE_FP32_KAHAN 1 /* pair sums in FP32 (exp2 on the transcendental unit, Hermite
+                            factors with exact integer coefficients) with
+                            Kahan-compensated per-thread sums; moments, cross-block
+                            reductions and Steps I-III, V, VII stay in FP64.  The one
+                            systematic error left is the FP32 rounding of log2(e)/2
+                            (relative 1.3e-8) in the exponent                            */
+#define KDE_FP32_KAHAN_EXACT 2 /* as KDE_FP32_KAHAN with log2(e)/2 carried as two FP32
+                                  terms (one more VALU op per pair)                    */
+
+#define KDE_MEM_HOST 0
+#define KDE_MEM_DEVICE 1
+
+#define KDE_F64 0
+#define KDE_F32 1
+
+typedef struct kde_ctx kde_ctx;
+typedef void* kde_stream;
+
+typedef struct {
+    int32_t device;     /* HIP device ordinal (default 0)                                  */
+    int32_t precision;  /* KDE_FP64_PLAIN (default), KDE_FP32_KAHAN or KDE_FP32_KAHAN_EXACT  */
+    int64_t mem_budget; /* bytes of device workspace this context may hold; 0 = no limit    */
+    const char* tune_table; /* path of an autotune table written by kde_autotune, or NULL
+                               for the built-in tile configuration                          */
+    int32_t rows_per_lane;   /* 0 = from the tune table / default; else 1, 2 or 4          */
+    int32_t blocks_per_cu;   /* 0 = from the tune table / occupancy; else 1..16            */
+    int32_t target_items;    /* 0 = default; pair work items per stage for large n         */
+    int32_t reserved;
+} kde_options;
+
+/* The outputs of Algorithm 1 for one sample.  psi6/psi4 are the estimates of
+ * Steps IV and VI; psi8 is Step II's normal-scale estimate. */
+typedef struct {
+    double h;       /* Step VII bandwidth (for kde_psi_ex-style calls: NaN)            */
+    double mean;    /* sample mean                                                      */
+    double sigma;   /* Step I standard deviation (divisor n - 1)                        */
+    double psi8;    /* Step II                                                          */
+    double g1;      /* Step III                                                         */
+    double psi6;    /* Step IV                                                          */
+    double g2;      /* Step V                                                           */
+    double psi4;    /* Step VI                                                          */
+    int32_t status; /* KDE_OK or the KDE_E* code for this sample                        */
+    int32_t reserved;
+} kde_result;
+
+/* -------------------------------------------------------------- utilities */
+const char* kde_version(void);
+int kde_last_error(void);                  /* last status set on this thread */
+const char* kde_last_error_message(void);  /* human-readable detail for it   */
+const char* kde_strerror(int code);
+
+/* Fill *opt with the defaults listed above. */
+void kde_options_init(kde_options* opt);
+
+/* Create a context on opt->device (opt may be NULL for defaults).  The
+ * context owns its device workspace (work lists, per-item partial sums,
+ * per-sample state), cached hipGraphs and the tile configuration. */
+int kde_ctx_create(kde_ctx** out, const kde_options* opt);
+void kde_ctx_destroy(kde_ctx* ctx);
+
+/* Tile configuration actually in use: rows per lane, threads per block,
+ * rows per tile, persistent blocks per CU. */
+int kde_ctx_config(const kde_ctx* ctx, int32_t* rows_per_lane, int32_t* block_threads,
+                   int32_t* tile_rows, int32_t* blocks_per_cu);
+
+/* Device timeline of sample `sample` of the last synchronous call on this
+ * context: ms[k] = milliseconds from the start of the sample's first work
+ * item to the moment stage k published its result (k = 0: mean, 1: sigma
+ * and g1 (Steps I-III), 2: Psi6 and g2 (Steps IV-V), 3: Psi4 and h (Steps
+ * VI-VII)); -1 for a stage that did not run.  From the GPU's 100 MHz clock. */
+int kde_ctx_last_timeline(const kde_ctx* ctx, int64_t sample, double* ms);
+
+/* ------------------------------------------------------- literal calls */
+
+/* Psi_r(g) of equations (6)-(7) (Steps IV/VI with a caller-chosen g) for
+ * r in {4, 6}: host pointer x[0..n), n >= 1, g > 0.  Synchronous, FP64
+ * plain, default context.  Returns NaN on error. */
+double kde_psi(const double* x, int64_t n, int r, double g);
+
+/* h of Algorithm 1 (Steps I-VII) for host samples x[0..n), n >= 2.
+ * Synchronous, FP64 plain, default context.  Returns NaN on error. */
+double kde_plugin_bandwidth(const double* x, int64_t n);
+
+/* --------------------------------------------------------- context calls */
+
+/* Psi_r(g) for samples x (mem_kind KDE_MEM_HOST/DEVICE, dtype KDE_F64/F32),
+ * in the context's precision.  *out receives the value.  Synchronous. */
+int kde_psi_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r,
+               double g, kde_stream stream, double* out);
+
+/* Algorithm 1 for one sample; *out receives every intermediate.  The result's
+ * status field repeats the return code.  Synchronous. */
+int kde_plugin_bandwidth_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype,
+                            kde_stream stream, kde_result* out);
+
+/* Algorithm 1 for count independent samples xs[k][0..ns[k]) (all host or all
+ * device pointers, FP64), in ONE launch of the persistent kernel (replayed
+ * from a cached hipGraph when the same batch is seen again).  out[k] is
+ * filled for every k; the return value is KDE_OK when the launch itself
+ * succeeded, and per-sample failures are reported in out[k].status.  Each
+ * out[k] is bitwise identical to what kde_plugin_bandwidth_ex returns for the
+ * same sample on the same context.  Synchronous. */
+int kde_plugin_bandwidth_batch(kde_ctx* ctx, const void* const* xs, const int64_t* ns,
+                               int64_t count, int mem_kind, kde_result* out, kde_stream stream);
+
+/* ---------------------------------------------- work decomposition / shards */
+
+/* Number of pair work items of one Psi stage for a sample of size n on this
+ * context (the decomposition depends on n and the tile configuration only). */
+int64_t kde_psi_num_items(const kde_ctx* ctx, int64_t n);
+
+/* Rectangle of the pair matrix covered by pair item `item`: rows [r0, r1),
+ * columns [c0, c1), of which only the pairs with column > row are summed. */
+int kde_psi_item_geometry(const kde_ctx* ctx, int64_t n, int64_t item, int64_t* r0,
+                          int64_t* r1, int64_t* c0, int64_t* c1);
+
+/* Partial sum of one Psi stage over the contiguous pair items
+ * [item_begin, item_end):  *partial = sum over those items' pairs i < j of
+ * K^(r)((x_i - x_j)/g), in the context's precision with an FP64 total.
+ * This is one shard of Step IV/VI: the shards of a partition of
+ * [0, kde_psi_num_items) add up to the full strict-upper-triangle sum.
+ * Synchronous. */
+int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r,
+                  double g, int64_t item_begin, int64_t item_end, kde_stream stream,
+                  double* partial);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDEPLUGIN_H */

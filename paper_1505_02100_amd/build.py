@@ -1,0 +1,71 @@
+"""Build libkdeplugin.so (HIP for gfx950) in-tree.
+
+hipcc cross-compiles for gfx950 without a GPU.  Packed FP32 VALU forms are
+disabled for every HIP translation unit (the host pass warns that it does not
+know the feature; that warning is harmless).
+
+The library is linked against the HIP runtime that PyTorch ships
+(torch/lib/libamdhip64.so), so it only uses entry points that runtime
+exports.  Its dependency is recorded by soname (libamdhip64.so.7); when torch
+is imported first, that soname resolves to torch's already loaded runtime, so
+torch tensors' device pointers and streams and the library's launches share
+one HIP runtime instance (the Python binding imports torch before loading the
+library and checks that only one runtime is mapped).  A C program without
+torch resolves the soname to the system ROCm runtime instead.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libkdeplugin.so")
+
+SOURCES = ["kde_device.hip", "kde_host.cpp"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-fno-gpu-rdc",
+]
+
+
+def torch_hip_libdir() -> str:
+    """Directory of the HIP runtime bundled with the installed PyTorch."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.submodule_search_locations:
+        raise RuntimeError("PyTorch is required: its HIP runtime is the one the library links")
+    d = os.path.join(list(spec.submodule_search_locations)[0], "lib")
+    if not os.path.exists(os.path.join(d, "libamdhip64.so")):
+        raise RuntimeError(f"no libamdhip64.so in {d}")
+    return d
+
+
+def build(verbose: bool = False) -> str:
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    tlib = torch_hip_libdir()
+    cmd = ["g++", "-shared", "-fPIC", "-o", tmp, *objs, "-L" + tlib, "-l:libamdhip64.so",
+           "-Wl,--no-undefined", "-lstdc++", "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

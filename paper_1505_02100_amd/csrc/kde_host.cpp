@@ -1,0 +1,734 @@
+// Host runtime and C ABI of libkdeplugin.
+//
+// A context owns a small cache of "plans".  A plan is everything one launch
+// of the persistent kernel needs for a fixed problem shape: the ordered work
+// list, the per-sample descriptors, state records, partial-sum slots, the
+// work ticket, and a hipGraph (init kernel + persistent kernel) that is
+// replayed whenever the same shape comes back.  Only the descriptors (sample
+// pointers) are refreshed between replays, and only when they changed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kde_internal.h"
+
+namespace kde {
+hipError_t launch_init(State* states, int32_t count, uint32_t* ticket, hipStream_t s);
+hipError_t launch_persistent(int prec, int R, int grid, hipStream_t s, const LaunchArgs& a);
+hipError_t persistent_occupancy(int prec, int R, int* blocks_per_cu);
+}  // namespace kde
+
+using namespace kde;
+
+// ----------------------------------------------------------------- errors
+namespace {
+thread_local int t_err = KDE_OK;
+thread_local std::string t_msg;
+
+int set_err(int code, const std::string& msg) {
+    t_err = code;
+    t_msg = msg;
+    return code;
+}
+int ok() {
+    t_err = KDE_OK;
+    t_msg.clear();
+    return KDE_OK;
+}
+int hip_fail(hipError_t e, const char* what) {
+    return set_err(KDE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(call)                                   \
+    do {                                               \
+        hipError_t _e = (call);                        \
+        if (_e != hipSuccess) return hip_fail(_e, #call); \
+    } while (0)
+
+const double kPi = 3.14159265358979323846;
+constexpr int kBlock = 256;           // threads per block of the persistent kernel
+constexpr int64_t kMomentChunk = 65536;
+constexpr int64_t kDefaultTarget = 16384;
+constexpr uint64_t kTimeoutTicks = 20ull * 100000000ull;  // 20 s at the 100 MHz wall clock
+
+// ------------------------------------------------------------ device buffer
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int ensure(size_t need, const char* what) {
+        if (need <= bytes) return KDE_OK;
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+            bytes = 0;
+        }
+        hipError_t e = hipMalloc(&p, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(KDE_ENOMEM, std::string("hipMalloc ") + what + ": " + hipGetErrorString(e));
+        }
+        bytes = need;
+        return KDE_OK;
+    }
+};
+
+PolyConsts make_consts() {
+    // exp(-y^2/2) = 2^(-k y^2) with k = log2(e)/2 (see kde_device.hip)
+    const double k = 0.5 / std::log(2.0);
+    const double rt2pi = std::sqrt(2.0 * kPi);
+    PolyConsts pc{};
+    pc.k_hi = (float)k;
+    pc.k_lo = (float)(k - (double)pc.k_hi);
+    const double kx = (double)pc.k_hi + (double)pc.k_lo;
+    // e = exp2(-k Z) with Z = y^2 - 5 (r = 6) or y^2 - 3 (r = 4)
+    pc.f6 = std::exp2(-5.0 * (double)pc.k_hi) / rt2pi;
+    pc.f4 = std::exp2(-3.0 * (double)pc.k_hi) / rt2pi;
+    pc.f6x = std::exp2(-5.0 * kx) / rt2pi;
+    pc.f4x = std::exp2(-3.0 * kx) / rt2pi;
+    return pc;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plans
+struct Plan {
+    std::string key;
+    int32_t count = 0;                // samples
+    std::vector<Item> items;
+    std::vector<Desc> descs;          // host copy of what is on the device
+    bool descs_valid = false;
+    DevBuf d_items, d_descs, d_states, d_slots, d_ticket;
+    State* h_states = nullptr;        // pinned
+    int64_t n_slots = 0;
+    hipGraphExec_t exec = nullptr;
+    int grid = 0;
+    ~Plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (h_states) (void)hipHostFree(h_states);
+    }
+    size_t device_bytes() const {
+        return d_items.bytes + d_descs.bytes + d_states.bytes + d_slots.bytes + d_ticket.bytes;
+    }
+};
+
+struct kde_ctx {
+    std::vector<State> last_states;           // device state records of the last call
+    int device = 0;
+    int precision = KDE_FP64_PLAIN;
+    int64_t mem_budget = 0;
+    int R = 1;
+    int blocks_per_cu = 0;
+    int64_t target_items = kDefaultTarget;
+    int cus = 0;
+    PolyConsts pc{};
+    std::list<std::unique_ptr<Plan>> plans;   // most recently used first
+    size_t max_plans = 16;
+    DevBuf x_stage;                           // host samples copied here
+    std::vector<DevBuf> batch_stage;          // unused slots kept for reuse
+};
+
+namespace {
+
+// Pair-item decomposition of the strict upper triangle for a sample of size n.
+struct PairGeom {
+    int64_t n, TI, W, RB;
+};
+
+PairGeom pair_geom(const kde_ctx* c, int64_t n) {
+    PairGeom g{};
+    g.n = n;
+    g.TI = (int64_t)kBlock * c->R;
+    g.RB = (n + g.TI - 1) / g.TI;
+    const double P = 0.5 * (double)n * (double)(n - 1);
+    const double want = P / ((double)g.TI * (double)std::max<int64_t>(1, c->target_items));
+    int64_t W = 64;
+    while ((double)W < want && W < ((int64_t)1 << 40)) W <<= 1;
+    g.W = W;
+    return g;
+}
+
+int64_t pair_items_in_row(const PairGeom& g, int64_t rb) {
+    const int64_t cols = g.n - rb * g.TI;
+    return cols > 0 ? (cols + g.W - 1) / g.W : 0;
+}
+
+int64_t pair_item_count(const PairGeom& g) {
+    int64_t tot = 0;
+    for (int64_t rb = 0; rb < g.RB; ++rb) tot += pair_items_in_row(g, rb);
+    return tot;
+}
+
+// Item k of the pair enumeration (row-block major) -> (rb, cb).
+bool pair_item_at(const PairGeom& g, int64_t k, int64_t* rb, int64_t* cb) {
+    for (int64_t r = 0; r < g.RB; ++r) {
+        const int64_t m = pair_items_in_row(g, r);
+        if (k < m) {
+            *rb = r;
+            *cb = k;
+            return true;
+        }
+        k -= m;
+    }
+    return false;
+}
+
+struct SampleSpec {
+    const void* x;
+    int64_t n;
+    int32_t dtype;
+    int32_t mode;
+    int32_t psi_r;
+    double psi_g;
+    int64_t item_begin, item_end;  // pair-item range (MODE_PSI); [0, -1) = all
+};
+
+int64_t moment_chunk(int64_t n) {
+    return std::max<int64_t>(kMomentChunk, (n + 1023) / 1024);
+}
+
+// Build the ordered work list: stage-major over samples (largest first), so
+// that every item a later stage waits on is handed out long before it.
+void build_items(const kde_ctx* c, Plan& p, const std::vector<SampleSpec>& ss) {
+    const int32_t m = (int32_t)ss.size();
+    p.count = m;
+    p.descs.assign(m, Desc{});
+    std::vector<int32_t> order(m);
+    for (int32_t k = 0; k < m; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return ss[a].n > ss[b].n; });
+    for (int32_t k = 0; k < m; ++k) {
+        Desc& d = p.descs[k];
+        d.x = ss[k].x;
+        d.n = ss[k].n;
+        d.dtype = ss[k].dtype;
+        d.mode = ss[k].mode;
+        d.psi_r = ss[k].psi_r;
+        d.psi_g = ss[k].psi_g;
+        d.chunk = (int32_t)moment_chunk(ss[k].n);
+        const PairGeom g = pair_geom(c, ss[k].n);
+        d.W = g.W;
+        const int64_t nm = (ss[k].n + d.chunk - 1) / d.chunk;
+        d.n_items[ST_SUM] = (int32_t)nm;
+        d.n_items[ST_SSQ] = (int32_t)nm;
+        if (ss[k].mode == MODE_PLUGIN) {
+            const int64_t np = pair_item_count(g);
+            d.n_items[ST_PSI6] = (int32_t)np;
+            d.n_items[ST_PSI4] = (int32_t)np;
+        } else {
+            const int64_t np = pair_item_count(g);
+            const int64_t b = std::max<int64_t>(0, ss[k].item_begin);
+            const int64_t e = ss[k].item_end < 0 ? np : std::min(np, ss[k].item_end);
+            const int st = ss[k].psi_r == 6 ? ST_PSI6 : ST_PSI4;
+            d.n_items[st] = (int32_t)std::max<int64_t>(0, e - b);
+        }
+    }
+    // slots: contiguous per (sample, stage)
+    int64_t slot = 0;
+    for (int32_t k = 0; k < m; ++k)
+        for (int s = 0; s < NUM_STAGES; ++s) {
+            p.descs[k].slot_base[s] = slot;
+            slot += p.descs[k].n_items[s];
+        }
+    p.n_slots = slot;
+    p.items.clear();
+    p.items.reserve((size_t)slot);
+    for (int s = 0; s < NUM_STAGES; ++s) {
+        for (int32_t oi = 0; oi < m; ++oi) {
+            const int32_t k = order[oi];
+            const Desc& d = p.descs[k];
+            const int32_t cnt = d.n_items[s];
+            if (cnt == 0) continue;
+            int32_t wait = -1;
+            if (s == ST_SSQ) wait = ST_SUM;
+            if (s == ST_PSI6) wait = ST_SSQ;
+            if (s == ST_PSI4) wait = d.mode == MODE_PLUGIN ? ST_PSI6 : ST_SSQ;
+            if (s == ST_SUM || s == ST_SSQ) {
+                for (int32_t q = 0; q < cnt; ++q)
+                    p.items.push_back(Item{k, s, wait, q, 0, 0, d.slot_base[s] + q});
+            } else {
+                const PairGeom g = pair_geom(c, d.n);
+                const int64_t first = d.mode == MODE_PLUGIN ? 0 : std::max<int64_t>(0, ss[k].item_begin);
+                int64_t rb = 0, cb = 0;
+                pair_item_at(g, first, &rb, &cb);
+                for (int32_t q = 0; q < cnt; ++q) {
+                    p.items.push_back(Item{k, s, wait, (int32_t)rb, (int32_t)cb, 0, d.slot_base[s] + q});
+                    if (++cb >= pair_items_in_row(g, rb)) {
+                        ++rb;
+                        cb = 0;
+                    }
+                }
+            }
+        }
+    }
+}
+
+int grid_for(const kde_ctx* c, int64_t n_items) {
+    int g = c->cus * std::max(1, c->blocks_per_cu);
+    if (n_items < g) g = (int)std::max<int64_t>(1, n_items);
+    return g;
+}
+
+int total_plan_bytes(const kde_ctx* c, size_t extra, size_t* out) {
+    size_t tot = extra + c->x_stage.bytes;
+    for (auto& p : c->plans) tot += p->device_bytes();
+    *out = tot;
+    return KDE_OK;
+}
+
+// Allocate and upload a freshly built plan.
+int upload_plan(kde_ctx* c, Plan& p) {
+    const size_t need = sizeof(Item) * std::max<size_t>(1, p.items.size()) +
+                        sizeof(Desc) * std::max(1, p.count) + sizeof(State) * std::max(1, p.count) +
+                        sizeof(Slot) * (size_t)std::max<int64_t>(1, p.n_slots) + 256;
+    if (c->mem_budget > 0) {
+        size_t have = 0;
+        total_plan_bytes(c, need, &have);
+        while (have > (size_t)c->mem_budget && !c->plans.empty()) {
+            c->plans.pop_back();  // evict least recently used
+            total_plan_bytes(c, need, &have);
+        }
+        if (have > (size_t)c->mem_budget)
+            return set_err(KDE_ENOMEM, "work list and partial sums exceed the context's memory budget");
+    }
+    int st;
+    if ((st = p.d_items.ensure(sizeof(Item) * std::max<size_t>(1, p.items.size()), "work list"))) return st;
+    if ((st = p.d_descs.ensure(sizeof(Desc) * std::max(1, p.count), "descriptors"))) return st;
+    if ((st = p.d_states.ensure(sizeof(State) * std::max(1, p.count), "states"))) return st;
+    if ((st = p.d_slots.ensure(sizeof(Slot) * (size_t)std::max<int64_t>(1, p.n_slots), "slots"))) return st;
+    if ((st = p.d_ticket.ensure(256, "ticket"))) return st;
+    HIPCHK(hipHostMalloc((void**)&p.h_states, sizeof(State) * std::max(1, p.count), hipHostMallocDefault));
+    if (!p.items.empty())
+        HIPCHK(hipMemcpy(p.d_items.p, p.items.data(), sizeof(Item) * p.items.size(), hipMemcpyHostToDevice));
+    p.grid = grid_for(c, (int64_t)p.items.size());
+    return KDE_OK;
+}
+
+LaunchArgs args_for(const kde_ctx* c, Plan& p) {
+    LaunchArgs a{};
+    a.items = (const Item*)p.d_items.p;
+    a.n_items = (uint32_t)p.items.size();
+    a.descs = (const Desc*)p.d_descs.p;
+    a.states = (State*)p.d_states.p;
+    a.slots = (Slot*)p.d_slots.p;
+    a.ticket = (uint32_t*)p.d_ticket.p;
+    a.pc = c->pc;
+    a.timeout_ticks = kTimeoutTicks;
+    return a;
+}
+
+// Record init + persistent kernel into a graph on first use; replay after.
+int run_plan(kde_ctx* c, Plan& p, hipStream_t s) {
+    if (!p.exec) {
+        hipStream_t cap;
+        HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const LaunchArgs a = args_for(c, p);
+            hipError_t e1 = launch_init((State*)p.d_states.p, p.count, (uint32_t*)p.d_ticket.p, cap);
+            hipError_t e2 = launch_persistent(c->precision, c->R, p.grid, cap, a);
+            e = hipStreamEndCapture(cap, &graph);
+            if (e == hipSuccess && (e1 != hipSuccess || e2 != hipSuccess)) e = e1 != hipSuccess ? e1 : e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&p.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) {
+            p.exec = nullptr;
+            return hip_fail(e, "graph capture of the persistent kernel");
+        }
+    }
+    HIPCHK(hipGraphLaunch(p.exec, s));
+    return KDE_OK;
+}
+
+Plan* find_plan(kde_ctx* c, const std::string& key) {
+    for (auto it = c->plans.begin(); it != c->plans.end(); ++it) {
+        if ((*it)->key == key) {
+            if (it != c->plans.begin()) c->plans.splice(c->plans.begin(), c->plans, it);
+            return c->plans.front().get();
+        }
+    }
+    return nullptr;
+}
+
+int get_plan(kde_ctx* c, const std::string& key, const std::vector<SampleSpec>& ss, Plan** out) {
+    Plan* p = find_plan(c, key);
+    if (!p) {
+        auto np = std::make_unique<Plan>();
+        np->key = key;
+        build_items(c, *np, ss);
+        int st = upload_plan(c, *np);
+        if (st) return st;
+        c->plans.push_front(std::move(np));
+        while (c->plans.size() > c->max_plans) c->plans.pop_back();
+        p = c->plans.front().get();
+    }
+    // refresh descriptors if the sample pointers (or psi parameters) changed
+    bool same = p->descs_valid && (int32_t)ss.size() == p->count;
+    for (size_t k = 0; same && k < ss.size(); ++k)
+        same = p->descs[k].x == ss[k].x && p->descs[k].psi_g == ss[k].psi_g;
+    if (!same) {
+        for (size_t k = 0; k < ss.size(); ++k) {
+            p->descs[k].x = ss[k].x;
+            p->descs[k].psi_g = ss[k].psi_g;
+        }
+        HIPCHK(hipMemcpy(p->d_descs.p, p->descs.data(), sizeof(Desc) * p->count, hipMemcpyHostToDevice));
+        p->descs_valid = true;
+    }
+    *out = p;
+    return KDE_OK;
+}
+
+void fill_result(const State& s, kde_result* r) {
+    r->h = s.h;
+    r->mean = s.mean;
+    r->sigma = s.sigma;
+    r->psi8 = s.psi8;
+    r->g1 = s.g1;
+    r->psi6 = s.psi6;
+    r->g2 = s.g2;
+    r->psi4 = s.psi4;
+    r->status = s.status;
+    r->reserved = 0;
+}
+
+int check_x(const void* x, int64_t n, int64_t nmin, int mem_kind, int dtype) {
+    if (!x) return set_err(KDE_EINVAL, "null sample pointer");
+    if (n < nmin)
+        return set_err(KDE_EINVAL, nmin == 2 ? "n must be at least 2 (Step I divides by n - 1)"
+                                            : "n must be at least 1");
+    if (n > ((int64_t)1 << 31) - 1) return set_err(KDE_EINVAL, "n must be below 2^31");
+    if (mem_kind != KDE_MEM_HOST && mem_kind != KDE_MEM_DEVICE) return set_err(KDE_EINVAL, "bad mem_kind");
+    if (dtype != KDE_F64 && dtype != KDE_F32) return set_err(KDE_EINVAL, "bad dtype");
+    return KDE_OK;
+}
+
+// Stage host samples into the context's device buffer (or pass device data).
+int stage_x(kde_ctx* c, const void* x, int64_t n, int mem_kind, int dtype, hipStream_t s,
+            const void** dev) {
+    if (mem_kind == KDE_MEM_DEVICE) {
+        *dev = x;
+        return KDE_OK;
+    }
+    const size_t bytes = (size_t)n * (dtype == KDE_F64 ? 8 : 4);
+    int st = c->x_stage.ensure(bytes, "sample staging buffer");
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(c->x_stage.p, x, bytes, hipMemcpyHostToDevice, s));
+    *dev = c->x_stage.p;
+    return KDE_OK;
+}
+
+int finish(kde_ctx* c, Plan& p, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(p.h_states, p.d_states.p, sizeof(State) * p.count, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->last_states.assign(p.h_states, p.h_states + p.count);
+    return KDE_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+std::string key_single(const char* tag, int64_t n, int dtype, int extra1 = 0, int64_t e2 = 0,
+                       int64_t e3 = 0) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s:n=%lld:t=%d:%d:%lld:%lld", tag, (long long)n, dtype, extra1,
+                  (long long)e2, (long long)e3);
+    return buf;
+}
+
+std::mutex g_default_mu;
+kde_ctx* g_default = nullptr;
+
+kde_ctx* default_ctx() {
+    if (!g_default) {
+        kde_ctx* c = nullptr;
+        if (kde_ctx_create(&c, nullptr) == KDE_OK) g_default = c;
+    }
+    return g_default;
+}
+
+int psi_common(kde_ctx* c, const void* x, int64_t n, int mem_kind, int dtype, int r, double g,
+               int64_t b, int64_t e, hipStream_t s, State* out) {
+    int st = check_x(x, n, 1, mem_kind, dtype);
+    if (st) return st;
+    if (r != 4 && r != 6) return set_err(KDE_EINVAL, "r must be 4 or 6");
+    if (!(g > 0.0) || !std::isfinite(g)) return set_err(KDE_EINVAL, "g must be finite and positive");
+    DeviceGuard dg(c->device);
+    const void* dx = nullptr;
+    if ((st = stage_x(c, x, n, mem_kind, dtype, s, &dx))) return st;
+    SampleSpec sp{dx, n, dtype, MODE_PSI, r, g, b, e};
+    Plan* p = nullptr;
+    if ((st = get_plan(c, key_single("psi", n, dtype, r, b, e), {sp}, &p))) return st;
+    if ((st = run_plan(c, *p, s))) return st;
+    if ((st = finish(c, *p, s))) return st;
+    *out = p->h_states[0];
+    return KDE_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* kde_version(void) { return "libkdeplugin 0.1 (gfx950)"; }
+
+int kde_last_error(void) { return t_err; }
+
+const char* kde_last_error_message(void) { return t_msg.c_str(); }
+
+const char* kde_strerror(int code) {
+    switch (code) {
+    case KDE_OK: return "ok";
+    case KDE_EINVAL: return "invalid argument";
+    case KDE_ENONFINITE: return "non-finite sample value";
+    case KDE_EDEGENERATE: return "degenerate sample (zero spread or failed sign invariant)";
+    case KDE_ENOMEM: return "out of memory or over budget";
+    case KDE_EDEVICE: return "HIP runtime error";
+    case KDE_ETIMEOUT: return "in-kernel stage wait timed out";
+    case KDE_EBUSY: return "busy";
+    default: return "unknown status";
+    }
+}
+
+void kde_options_init(kde_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->device = 0;
+    opt->precision = KDE_FP64_PLAIN;
+}
+
+int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
+    if (!out) return set_err(KDE_EINVAL, "null output pointer");
+    *out = nullptr;
+    kde_options o;
+    kde_options_init(&o);
+    if (opt) o = *opt;
+    if (o.precision != KDE_FP64_PLAIN && o.precision != KDE_FP32_KAHAN &&
+        o.precision != KDE_FP32_KAHAN_EXACT)
+        return set_err(KDE_EINVAL, "bad precision");
+    if (o.rows_per_lane != 0 && o.rows_per_lane != 1 && o.rows_per_lane != 2 && o.rows_per_lane != 4)
+        return set_err(KDE_EINVAL, "rows_per_lane must be 0, 1, 2 or 4");
+    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 16) return set_err(KDE_EINVAL, "blocks_per_cu out of range");
+    if (o.mem_budget < 0 || o.target_items < 0) return set_err(KDE_EINVAL, "negative option");
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) return set_err(KDE_EDEVICE, "no HIP device available");
+    if (o.device < 0 || o.device >= ndev) return set_err(KDE_EINVAL, "device ordinal out of range");
+    auto c = std::make_unique<kde_ctx>();
+    c->device = o.device;
+    c->precision = o.precision;
+    c->mem_budget = o.mem_budget;
+    c->R = o.rows_per_lane ? o.rows_per_lane : (o.precision != KDE_FP64_PLAIN ? 2 : 1);
+    c->target_items = o.target_items ? o.target_items : kDefaultTarget;
+    c->pc = make_consts();
+    DeviceGuard dg(c->device);
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, c->device));
+    c->cus = prop.multiProcessorCount;
+    int occ = 0;
+    HIPCHK(persistent_occupancy(c->precision, c->R, &occ));
+    c->blocks_per_cu = o.blocks_per_cu ? o.blocks_per_cu : std::max(1, occ);
+    *out = c.release();
+    return ok();
+}
+
+void kde_ctx_destroy(kde_ctx* ctx) {
+    if (!ctx) return;
+    DeviceGuard dg(ctx->device);
+    (void)hipDeviceSynchronize();
+    delete ctx;
+}
+
+int kde_ctx_config(const kde_ctx* c, int32_t* rows_per_lane, int32_t* block_threads,
+                   int32_t* tile_rows, int32_t* blocks_per_cu) {
+    if (!c) return set_err(KDE_EINVAL, "null context");
+    if (rows_per_lane) *rows_per_lane = c->R;
+    if (block_threads) *block_threads = kBlock;
+    if (tile_rows) *tile_rows = kBlock * c->R;
+    if (blocks_per_cu) *blocks_per_cu = c->blocks_per_cu;
+    return ok();
+}
+
+int64_t kde_psi_num_items(const kde_ctx* c, int64_t n) {
+    if (!c || n < 1) {
+        set_err(KDE_EINVAL, "null context or n < 1");
+        return -1;
+    }
+    ok();
+    return pair_item_count(pair_geom(c, n));
+}
+
+int kde_psi_item_geometry(const kde_ctx* c, int64_t n, int64_t item, int64_t* r0, int64_t* r1,
+                          int64_t* c0, int64_t* c1) {
+    if (!c || n < 1 || item < 0) return set_err(KDE_EINVAL, "bad arguments");
+    const PairGeom g = pair_geom(c, n);
+    int64_t rb, cb;
+    if (!pair_item_at(g, item, &rb, &cb)) return set_err(KDE_EINVAL, "item index out of range");
+    const int64_t a = rb * g.TI;
+    const int64_t cs = a + cb * g.W;
+    if (r0) *r0 = a;
+    if (r1) *r1 = std::min(a + g.TI, n);
+    if (c0) *c0 = cs;
+    if (c1) *c1 = std::min(cs + g.W, n);
+    return ok();
+}
+
+int kde_psi_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r, double g,
+               kde_stream stream, double* out) {
+    if (!ctx || !out) return set_err(KDE_EINVAL, "null context or output");
+    State s{};
+    int st = psi_common(ctx, x, n, mem_kind, dtype, r, g, 0, -1, (hipStream_t)stream, &s);
+    if (st) return st;
+    if (s.status) return set_err(s.status, "Psi evaluation failed on the device");
+    *out = r == 6 ? s.psi6 : s.psi4;
+    return ok();
+}
+
+int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r, double g,
+                  int64_t item_begin, int64_t item_end, kde_stream stream, double* partial) {
+    if (!ctx || !partial) return set_err(KDE_EINVAL, "null context or output");
+    const int64_t np = n >= 1 ? pair_item_count(pair_geom(ctx, n)) : 0;
+    if (item_begin < 0 || item_end < item_begin || item_end > np)
+        return set_err(KDE_EINVAL, "item range outside [0, kde_psi_num_items)");
+    if (item_begin == item_end) {
+        *partial = 0.0;
+        return ok();
+    }
+    State s{};
+    int st = psi_common(ctx, x, n, mem_kind, dtype, r, g, item_begin, item_end, (hipStream_t)stream, &s);
+    if (st) return st;
+    if (s.status) return set_err(s.status, "Psi range evaluation failed on the device");
+    *partial = r == 6 ? s.S6 : s.S4;
+    return ok();
+}
+
+int kde_plugin_bandwidth_ex(kde_ctx* c, const void* x, int64_t n, int mem_kind, int dtype,
+                            kde_stream stream, kde_result* out) {
+    if (!c || !out) return set_err(KDE_EINVAL, "null context or output");
+    std::memset(out, 0, sizeof(*out));
+    out->h = NAN;
+    int st = check_x(x, n, 2, mem_kind, dtype);
+    if (st) {
+        out->status = st;
+        return st;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(c->device);
+    const void* dx = nullptr;
+    if ((st = stage_x(c, x, n, mem_kind, dtype, s, &dx))) return out->status = st;
+    SampleSpec sp{dx, n, dtype, MODE_PLUGIN, 0, 0.0, 0, -1};
+    Plan* p = nullptr;
+    if ((st = get_plan(c, key_single("plugin", n, dtype), {sp}, &p))) return out->status = st;
+    if ((st = run_plan(c, *p, s))) return out->status = st;
+    if ((st = finish(c, *p, s))) return out->status = st;
+    fill_result(p->h_states[0], out);
+    if (out->status) {
+        out->h = NAN;
+        return set_err(out->status, "bandwidth selection failed on the device");
+    }
+    return ok();
+}
+
+int kde_plugin_bandwidth_batch(kde_ctx* c, const void* const* xs, const int64_t* ns, int64_t count,
+                               int mem_kind, kde_result* out, kde_stream stream) {
+    if (!c || !xs || !ns || !out || count < 1) return set_err(KDE_EINVAL, "bad batch arguments");
+    if (count > (1 << 24)) return set_err(KDE_EINVAL, "batch too large");
+    if (mem_kind != KDE_MEM_HOST && mem_kind != KDE_MEM_DEVICE) return set_err(KDE_EINVAL, "bad mem_kind");
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(c->device);
+    std::vector<SampleSpec> ss((size_t)count);
+    std::vector<int64_t> valid;
+    std::string key = "batch";
+    key.reserve(16 * (size_t)count);
+    size_t host_bytes = 0;
+    for (int64_t k = 0; k < count; ++k) {
+        std::memset(&out[k], 0, sizeof(kde_result));
+        out[k].h = NAN;
+        const int st = check_x(xs[k], ns[k], 2, mem_kind, KDE_F64);
+        out[k].status = st;
+        if (st == KDE_OK) {
+            valid.push_back(k);
+            host_bytes += (size_t)ns[k] * 8;
+        }
+    }
+    if (valid.empty()) return set_err(KDE_EINVAL, "no valid sample in the batch");
+    // host samples are packed into one device arena
+    size_t off = 0;
+    if (mem_kind == KDE_MEM_HOST) {
+        int st = c->x_stage.ensure(host_bytes, "batch staging arena");
+        if (st) return st;
+    }
+    std::vector<SampleSpec> vs;
+    vs.reserve(valid.size());
+    for (int64_t k : valid) {
+        const void* dx = xs[k];
+        if (mem_kind == KDE_MEM_HOST) {
+            dx = (char*)c->x_stage.p + off;
+            HIPCHK(hipMemcpyAsync((void*)dx, xs[k], (size_t)ns[k] * 8, hipMemcpyHostToDevice, s));
+            off += (size_t)ns[k] * 8;
+        }
+        vs.push_back(SampleSpec{dx, ns[k], KDE_F64, MODE_PLUGIN, 0, 0.0, 0, -1});
+        key += ":" + std::to_string(ns[k]);
+    }
+    Plan* p = nullptr;
+    int st;
+    if ((st = get_plan(c, key, vs, &p))) return st;
+    if ((st = run_plan(c, *p, s))) return st;
+    if ((st = finish(c, *p, s))) return st;
+    for (size_t q = 0; q < valid.size(); ++q) {
+        fill_result(p->h_states[q], &out[valid[q]]);
+        if (out[valid[q]].status) out[valid[q]].h = NAN;
+    }
+    return ok();
+}
+
+int kde_ctx_last_timeline(const kde_ctx* c, int64_t sample, double* ms) {
+    if (!c || !ms) return set_err(KDE_EINVAL, "null context or output");
+    if (sample < 0 || sample >= (int64_t)c->last_states.size())
+        return set_err(KDE_EINVAL, "sample index outside the last call");
+    const State& s = c->last_states[(size_t)sample];
+    for (int k = 0; k < NUM_STAGES; ++k)
+        ms[k] = s.t_fin[k] >= s.t_first && s.t_fin[k] ? (double)(s.t_fin[k] - s.t_first) * 1e-5 : -1.0;
+    return ok();
+}
+
+double kde_psi(const double* x, int64_t n, int r, double g) {
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    kde_ctx* c = default_ctx();
+    if (!c) return NAN;
+    double v = NAN;
+    if (kde_psi_ex(c, x, n, KDE_MEM_HOST, KDE_F64, r, g, nullptr, &v) != KDE_OK) return NAN;
+    return v;
+}
+
+double kde_plugin_bandwidth(const double* x, int64_t n) {
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    kde_ctx* c = default_ctx();
+    if (!c) return NAN;
+    kde_result r;
+    if (kde_plugin_bandwidth_ex(c, x, n, KDE_MEM_HOST, KDE_F64, nullptr, &r) != KDE_OK) return NAN;
+    return r.h;
+}
+
+}  // extern "C"

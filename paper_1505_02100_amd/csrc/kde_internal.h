@@ -1,0 +1,99 @@
+// Internal layout shared by the host runtime and the device code of
+// libkdeplugin.  Not part of the public interface.
+#pragma once
+
+#include <stdint.h>
+
+#include "kdeplugin.h"
+
+namespace kde {
+
+// Stages of one bandwidth selection, in dependency order (Algorithm 1).
+enum Stage : int32_t {
+    ST_SUM = 0,   // Step I, pass 1: sum of the samples -> mean
+    ST_SSQ = 1,   // Step I, pass 2: sum of squared deviations -> sigma; Steps II-III -> g1
+    ST_PSI6 = 2,  // Step IV pair sum; finaliser runs Step V -> g2
+    ST_PSI4 = 3,  // Step VI pair sum; finaliser runs Step VII -> h
+    NUM_STAGES = 4
+};
+
+enum Mode : int32_t {
+    MODE_PLUGIN = 0,  // Steps I-VII
+    MODE_PSI = 1,     // Steps I (for centring) + one pair stage with a given g
+};
+
+// Work item: one unit of one stage of one sample.  For the moment stages,
+// `a` is the chunk index.  For a pair stage, `a` is the row block and `b`
+// the column chunk within that row block's part of the upper triangle.
+struct Item {
+    int32_t ds;     // sample index in the descriptor table
+    int32_t stage;  // Stage
+    int32_t wait;   // stage whose finaliser must have published first, or -1
+    int32_t a;
+    int32_t b;
+    int32_t pad;
+    int64_t slot;   // index of this item's partial-sum slot
+};
+static_assert(sizeof(Item) == 32, "Item layout");
+
+// Per-sample description written by the host.
+struct Desc {
+    const void* x;          // samples on the device
+    int64_t n;
+    int32_t dtype;          // 0 = f64, 1 = f32
+    int32_t mode;           // Mode
+    int32_t psi_r;          // MODE_PSI: 4 or 6
+    int32_t chunk;          // elements per moment item
+    int64_t W;              // columns per pair item
+    int32_t n_items[NUM_STAGES];   // items of each stage present in the work list
+    int64_t slot_base[NUM_STAGES]; // first slot of each stage
+    double psi_g;           // MODE_PSI: the bandwidth g
+};
+
+// Per-sample state, zeroed by the init kernel and updated by the
+// persistent kernel (counters, flags and published scalars).
+struct State {
+    uint32_t done[NUM_STAGES];   // items finished per stage
+    uint32_t ready[NUM_STAGES];  // 1 once the stage's finaliser has published
+    int32_t status;
+    int32_t safe;                // clamp pair arguments (extreme spread)
+    double mean;
+    double scale;                // u = (x - mean) * scale for the current pair stage
+    double sigma, psi8, g1, psi6, g2, psi4, h;
+    double S6, S4;               // strict-upper-triangle kernel sums
+    double maxdev;               // max |x - mean|
+    uint64_t t_first;            // wall clock (100 MHz ticks) when the first item started
+    uint64_t t_fin[NUM_STAGES];  // wall clock when each stage's finaliser published
+};
+
+// Partial result of one work item.
+struct Slot {
+    double v;    // sum
+    double aux;  // moments pass 2: max |x - mean|; otherwise 0
+};
+
+// Constants of the FP32 pair evaluation (derivation in kde_device.hip) and
+// the FP64 factors that turn its sums into sums of K6 and K4.
+struct PolyConsts {
+    float k_hi;    // log2(e)/2 rounded to FP32
+    float k_lo;    // log2(e)/2 - k_hi rounded to FP32 (exact-k variant)
+    double f6;     // sum K6 = f6 * sum p e  with e = exp2(-k_hi Z)
+    double f4;     // sum K4 = f4 * sum p e
+    double f6x;    // the same with the two-term k
+    double f4x;
+};
+
+// Arguments of the persistent kernel.
+struct LaunchArgs {
+    const Item* items;
+    uint32_t n_items;
+    uint32_t pad0;
+    const Desc* descs;
+    State* states;
+    Slot* slots;
+    uint32_t* ticket;
+    PolyConsts pc;
+    uint64_t timeout_ticks;  // wall-clock ticks (100 MHz) an in-kernel wait may take
+};
+
+}  // namespace kde

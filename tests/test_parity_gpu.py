@@ -1,0 +1,217 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (relative):
+  * FP64 plain: h, Psi6, Psi4 within 1e-12.  Both sides evaluate the same
+    sums in FP64 in different orders, with different (faithfully rounded) exp
+    implementations and a reciprocal instead of a division for 1/g; the
+    rounding error of a sum of n^2 terms with cancellation factor
+    k = sum|terms| / |sum| stays below ~1e-14 k for the sizes tested.
+  * FP32 Kahan: h within 1e-6 (the bound the FP32 path is built to);
+    Psi6 and Psi4 within 2e-5 (their FP32 rounding is amplified by the
+    cancellation inside the Hermite factor and the sum).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_02100_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32_H = 1e-6
+TOL32_PSI = 2e-5
+
+
+@pytest.fixture(scope="module")
+def kp():
+    from paper_1505_02100_amd import kdeplugin
+    return kdeplugin
+
+
+@pytest.fixture(scope="module")
+def ctx64(kp):
+    c = kp.Context(kp.KDE_FP64_PLAIN)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx32(kp):
+    c = kp.Context(kp.KDE_FP32_KAHAN)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx32x(kp):
+    c = kp.Context(kp.KDE_FP32_KAHAN_EXACT)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def _check(res, ref, tol_h, tol_psi):
+    assert res.status == 0
+    assert _rel(res.sigma, ref.sigma) < 1e-13
+    assert _rel(res.g1, ref.g1) < 1e-13
+    assert _rel(res.psi6, ref.psi6) < tol_psi, (res.psi6, ref.psi6)
+    assert _rel(res.g2, ref.g2) < tol_psi
+    assert _rel(res.psi4, ref.psi4) < tol_psi, (res.psi4, ref.psi4)
+    assert _rel(res.h, ref.h) < tol_h, (res.h, ref.h, _rel(res.h, ref.h))
+
+
+RAGGED = [2, 3, 5, 63, 64, 65, 255, 256, 257, 511, 512, 513, 1000, 1023, 1024, 1025, 2047, 4097]
+
+
+@pytest.mark.parametrize("n", RAGGED)
+def test_plugin_fp64_ragged(ctx64, n):
+    x = synth.draw(["normal", "bimodal", "t3"][n % 3], n, 50 + n)
+    _check(ctx64.plugin_bandwidth(x), oracle.plugin(x), TOL64, TOL64)
+
+
+@pytest.mark.parametrize("n", RAGGED)
+def test_plugin_fp32_ragged(ctx32, ctx32x, n):
+    x = synth.draw(["normal", "bimodal", "t3"][n % 3], n, 50 + n)
+    ref = oracle.plugin(x)
+    _check(ctx32.plugin_bandwidth(x), ref, TOL32_H, TOL32_PSI)
+    _check(ctx32x.plugin_bandwidth(x), ref, TOL32_H, TOL32_PSI)
+
+
+def test_small_config_normal_1024(ctx64, ctx32):
+    # n = 1024 draws of N(0, 1), seed 0, checked in both precisions
+    x = synth.workload_single_normal(1024, 0)
+    ref = oracle.plugin(x)
+    _check(ctx64.plugin_bandwidth(x), ref, TOL64, TOL64)
+    _check(ctx32.plugin_bandwidth(x), ref, TOL32_H, TOL32_PSI)
+
+
+@pytest.mark.parametrize("n", [20000, 33333])
+def test_plugin_many_tiles(ctx64, ctx32, n):
+    x = synth.bimodal(n, 7)
+    ref = oracle.plugin(x)
+    _check(ctx64.plugin_bandwidth(x), ref, TOL64, TOL64)
+    _check(ctx32.plugin_bandwidth(x), ref, TOL32_H, TOL32_PSI)
+
+
+@pytest.mark.parametrize("r", [4, 6])
+@pytest.mark.parametrize("g", [0.05, 0.4, 3.0])
+def test_psi_fixed_g(ctx64, ctx32, r, g):
+    x = synth.student_t3(3001, 9)
+    ref = oracle.psi(x, r, g)
+    assert _rel(ctx64.psi(x, r, g), ref) < TOL64
+    assert _rel(ctx32.psi(x, r, g), ref) < TOL32_PSI
+
+
+def test_psi_literal_calls(kp):
+    x = synth.normal(777, 4)
+    assert _rel(kp.kde_psi(x, 6, 0.5), oracle.psi(x, 6, 0.5)) < TOL64
+    assert _rel(kp.kde_plugin_bandwidth(x), oracle.plugin(x).h) < TOL64
+    assert math.isnan(kp.kde_plugin_bandwidth([1.0]))
+    assert math.isnan(kp.kde_psi(x, 5, 0.5))
+
+
+def _abs_block_sum(x, r, g, r0, r1, c0, c1):
+    """sum |K^(r)((x_i - x_j)/g)| over the block's pairs j > i: the scale of
+    the rounding error bound (not a reference value)."""
+    from scipy import special
+    tot = 0.0
+    for i in range(r0, r1):
+        j0 = max(c0, i + 1)
+        if j0 >= c1:
+            continue
+        y = (x[i] - x[j0:c1]) / g
+        tot += np.sum(np.abs(special.eval_hermitenorm(r, y)) * np.exp(-0.5 * y * y)) / math.sqrt(2 * math.pi)
+    return tot
+
+
+def test_psi_range_items_match_oracle_blocks(ctx64, ctx32):
+    n = 9000
+    x = synth.student_t3(n, 3)
+    g = 0.3
+    for ctx, eps in ((ctx64, 1e-13), (ctx32, 2e-6)):
+        m = ctx.psi_num_items(n)
+        assert m > 4
+        for k in sorted({0, 1, m // 2, m - 2, m - 1}):
+            r0, r1, c0, c1 = ctx.psi_item_geometry(n, k)
+            got = ctx.psi_range(x, 6, g, k, k + 1)
+            ref = oracle.block_sum(x, 6, g, r0, r1, c0, c1)
+            bound = eps * _abs_block_sum(x, 6, g, r0, r1, c0, c1) + 1e-300
+            assert abs(got - ref) <= bound, (k, got, ref, bound)
+        # shards of a partition add up to the whole strict upper triangle
+        cuts = [0, m // 3, (2 * m) // 3, m]
+        total = sum(ctx.psi_range(x, 6, g, a, b) for a, b in zip(cuts[:-1], cuts[1:]))
+        ref = oracle.pair_sum(x, 6, g)
+        assert abs(total - ref) <= eps * _abs_block_sum(x, 6, g, 0, n, 0, n)
+
+
+def test_batch_equals_single_bitwise(ctx64, ctx32):
+    xs = [synth.draw(d, n, 100 + i) for i, (d, n) in
+          enumerate([("normal", 300), ("bimodal", 2048), ("t3", 77), ("normal", 5000), ("t3", 2)])]
+    for ctx in (ctx64, ctx32):
+        batch = ctx.plugin_bandwidth_batch(xs)
+        for x, b in zip(xs, batch):
+            s = ctx.plugin_bandwidth(x)
+            assert b.status == 0
+            assert (b.h, b.psi6, b.psi4, b.g2) == (s.h, s.psi6, s.psi4, s.g2)
+
+
+def test_batch_matches_oracle(ctx64, ctx32):
+    xs, _ = synth.workload_batch(count=24, master=31, n_lo=256, n_hi=4096)
+    r64 = ctx64.plugin_bandwidth_batch(xs)
+    r32 = ctx32.plugin_bandwidth_batch(xs)
+    for x, a, b in zip(xs, r64, r32):
+        ref = oracle.plugin(x)
+        _check(a, ref, TOL64, TOL64)
+        _check(b, ref, TOL32_H, TOL32_PSI)
+
+
+def test_deterministic_repeat(ctx32):
+    x = synth.bimodal(12345, 5)
+    a = ctx32.plugin_bandwidth(x)
+    b = ctx32.plugin_bandwidth(x)
+    assert (a.h, a.psi6, a.psi4) == (b.h, b.psi6, b.psi4)
+
+
+@pytest.mark.parametrize("a,b", [(1e3, -5e2), (-2.5, 7.0)])
+def test_scale_shift_equivariance(ctx64, ctx32, a, b):
+    x = synth.lognormal(5000, 12)
+    for ctx, tol in ((ctx64, 1e-12), (ctx32, 2e-6)):
+        h0 = ctx.plugin_bandwidth(x).h
+        h1 = ctx.plugin_bandwidth(a * x + b).h
+        assert _rel(h1, abs(a) * h0) < tol
+
+
+def test_error_cases(ctx64, ctx32, kp):
+    for ctx in (ctx64, ctx32):
+        r = ctx.plugin_bandwidth(np.array([1.0, np.nan, 2.0]), check=False)
+        assert r.status == kp.KDE_ENONFINITE and math.isnan(r.h)
+        r = ctx.plugin_bandwidth(np.array([1.0, np.inf, 2.0]), check=False)
+        assert r.status == kp.KDE_ENONFINITE
+        r = ctx.plugin_bandwidth(np.full(100, 3.25), check=False)
+        assert r.status == kp.KDE_EDEGENERATE
+        r = ctx.plugin_bandwidth(np.array([1.0]), check=False)
+        assert r.status == kp.KDE_EINVAL
+        with pytest.raises(kp.KdeError):
+            ctx.psi(np.ones(10), 4, -1.0)
+        # the context stays usable after errors
+        x = synth.normal(100, 1)
+        assert _rel(ctx.plugin_bandwidth(x).h, oracle.plugin(x).h) < TOL32_H
+
+
+def test_f32_input_and_device_tensors(ctx64, ctx32):
+    import torch
+    x = synth.bimodal(3000, 19)
+    ref = oracle.plugin(x)
+    xd = torch.from_numpy(x).cuda()
+    _check(ctx64.plugin_bandwidth(xd), ref, TOL64, TOL64)
+    _check(ctx32.plugin_bandwidth(xd), ref, TOL32_H, TOL32_PSI)
+    x32 = x.astype(np.float32)
+    ref32 = oracle.plugin(x32.astype(np.float64))
+    _check(ctx64.plugin_bandwidth(x32), ref32, TOL64, TOL64)
+    _check(ctx64.plugin_bandwidth(torch.from_numpy(x32).cuda()), ref32, TOL64, TOL64)
