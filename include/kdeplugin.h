@@ -64,12 +64,13 @@ extern "C" {
 
 /* ------------------------------------------------------------------ enums */
 #define KDE_FP64_PLAIN 0 /* pair sums in FP64 with the printed polynomials and FP64 exp      */
-#define KDE_FP32_KAHAN 1 /* pair sums in FP32 (exp2 on the transcendental unit, Hermite
-                            factors with exact integer coefficients) with
-                            Kahan-compensated per-thread sums; moments, cross-block
-                            reductions and Steps I-III, V, VII stay in FP64.  The one
-                            systematic error left is the FP32 rounding of log2(e)/2
-                            (relative 1.3e-8) in the exponent                            */
+#define KDE_FP32_KAHAN 1 /* pair terms in FP32 (exp2 on the transcendental unit, Hermite
+                            factors in y^2 with exact integer coefficients), compensated
+                            per-thread sums (FP32 accumulators of at most 4 terms folded
+                            into FP64); moments, cross-block reductions and Steps I-III,
+                            V, VII in FP64.  The one systematic error left by
+                            construction is the FP32 rounding of log2(e)/2 (relative
+                            1.3e-8) in the exponent                                       */
 #define KDE_FP32_KAHAN_EXACT 2 /* as KDE_FP32_KAHAN with log2(e)/2 carried as two FP32
                                   terms (one more VALU op per pair)                    */
 

@@ -13,37 +13,40 @@
 // 64 R columns per wave per diagonal item only.
 //
 // FP32 pair arithmetic.  The samples are prescaled once per tile load,
-// v = (x - mean) / g, in FP64 and then rounded to FP32, so d = v_i - v_j is
-// the kernel argument y = (x_i - x_j)/g of Steps IV and VI.  The Hermite
-// factors are depressed in Y = y^2 (Z = Y - 5, resp. Z = Y - 3):
-//     He6(y) = y^6 - 15 y^4 + 45 y^2 - 15 = Z^3 - 30 Z - 40,
-//     He4(y) = y^4 - 6 y^2 + 3            = Z^2 - 6,
-// so every polynomial coefficient is a small integer, exact in FP32.  The
-// Gaussian factor is exp(-Y/2) = 2^(-k Y), k = log2(e)/2, evaluated as
-// exp2(-k Z) (one v_exp_f32) times the constant 2^(-5k) (resp. 2^(-3k)),
-// which is applied once to the FP64 total together with 1/sqrt(2 pi).  Per
-// pair (r = 6):
-//     d = vi - vj; Z = fma(d, d, -5); a = k Z; e = exp2(-a);
-//     q = fma(Z, Z, -30); p = fma(q, Z, -40); acc = fma(p, e, acc)
-// which is 6 VALU + 1 transcendental (r = 4 drops q: 5 + 1).  Why this form:
-// the sums of K6 and K4 over all pairs cancel heavily (sum |K| / |sum K| is
-// in the hundreds already at n = 1024 and grows as g shrinks), so any
-// systematic error in the kernel's shape is amplified by that factor, while
-// rounding errors that vary from pair to pair average out.  With integer
-// coefficients the only systematic error left is the FP32 rounding of k
-// (relative 1.3e-8), i.e. the Gaussian evaluated at a bandwidth larger by
-// 7e-9 than the polynomial.  The EXACT_K variant removes even that with a
-// two-term k (a = fma(Z, k_hi, Z k_lo)) at one more VALU op per pair.
-// The FP32 value of a sample carries a rounding error that enters every
-// pair of that sample the same way; summed over its n pairs it no longer
-// averages out, and the cancellation factor makes it the dominant error at
-// large n.  Each item therefore centres its rows and columns on its own
-// offset, mean + g tau(row block) with tau a generic value in [-1/4, 1/4)
-// (a golden-ratio sequence): the differences are unchanged, but a sample's
-// rounding differs from item to item, so those errors average out too.
-// Per lane, each row keeps FP32 partial sums over chunks of 64 columns that
-// are folded into a Kahan-compensated FP32 (sum, compensation) pair.  The
-// lane totals are reduced in FP64 in a fixed order.
+// v = (x - c) / g, in FP64 and then rounded to FP32, so d = v_i - v_j is the
+// kernel argument y = (x_i - x_j)/g of Steps IV and VI.  With Y = y^2:
+//     He6(y) = ((Y - 15) Y + 45) Y - 15,    He4(y) = (Y - 6) Y + 3,
+// whose coefficients are small integers, exact in FP32, and the Gaussian
+// factor exp(-Y/2) = 2^(-k Y), k = log2(e)/2, is one v_exp_f32.  Per pair
+// (r = 6):
+//     d = vi - vj; Y = d d; a = k Y; e = exp2(-a);
+//     q = Y - 15; q = fma(q, Y, 45); p = fma(q, Y, -15); acc = fma(p, e, acc)
+// which is 7 VALU + 1 transcendental (r = 4 drops one fma: 6 + 1); 1/sqrt(2 pi)
+// is applied once to the FP64 total.
+//
+// Why this form.  The sums of K6 and K4 over all pairs cancel heavily:
+// sum |K| / |sum K| is in the hundreds at n = 1024 and grows like g^-6, to
+// about 1e4 at n = 2^20.  A systematic error of relative size b per term
+// therefore costs b times that factor, while errors that vary randomly from
+// pair to pair average out.  Measured on gfx950 at n = 2^20, the systematic
+// sources were, in order: FP32 running sums that take many terms (rounding
+// of a growing partial sum is not unbiased; 32 terms per accumulator cost
+// 2e-5 on Psi6), irrational polynomial coefficients rounded to FP32 (this
+// is why all coefficients are integers here), the absorption of a small
+// y^2 into an additive shift (why the polynomial is not depressed), and a
+// small bias of v_exp_f32 (mean relative error about -3e-9).  So each row
+// keeps four FP32 accumulators (one per column of an LDS b128 read) that take
+// at most kFold terms each before they are added into the lane's FP64 sum.
+// The one systematic error left by construction is the FP32 rounding of k
+// (relative 1.3e-8, i.e. the Gaussian taken at a bandwidth 7e-9 larger than
+// the polynomial's); the EXACT_K variant removes it with a two-term k,
+// a = fma(Y, k_hi, Y k_lo), at one more VALU op per pair.
+//
+// Each item also centres its rows and columns on its own offset,
+// c = mean + g tau(row block) with tau a generic value in [-1/4, 1/4) (a
+// golden-ratio sequence): the differences are unchanged, but a sample's FP32
+// rounding differs from item to item instead of entering all its n pairs
+// the same way.
 //
 // FP64 pair arithmetic is the plain printed form: t = y^2,
 // p = ((t - 15) t + 45) t - 15 (resp. (t - 6) t + 3), exp(-t/2), FP64 sums.
@@ -162,12 +165,25 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 }
 
 // ------------------------------------------------------------- moments
+// Each thread reads U values per round so that the loads of a round are in
+// flight together; per-thread order is fixed, so the result is deterministic.
+constexpr int kMomentUnroll = 8;
+
 template <int BLOCK>
 __device__ double moment_sum(const View& d, int32_t chunk_idx, double* red) {
     const int64_t a = (int64_t)chunk_idx * d.chunk;
     const int64_t b = min(a + (int64_t)d.chunk, d.n);
     double s = 0.0;
-    for (int64_t i = a + threadIdx.x; i < b; i += BLOCK) s += load_x(d.x, d.dtype, i);
+    for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += (int64_t)BLOCK * kMomentUnroll) {
+        double v[kMomentUnroll];
+#pragma unroll
+        for (int u = 0; u < kMomentUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * BLOCK;
+            v[u] = i < b ? load_x(d.x, d.dtype, i) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kMomentUnroll; ++u) s += v[u];
+    }
     return block_sum<BLOCK>(s, red);
 }
 
@@ -177,77 +193,81 @@ __device__ void moment_ssq(const View& d, int32_t chunk_idx, double mean, double
     const int64_t a = (int64_t)chunk_idx * d.chunk;
     const int64_t b = min(a + (int64_t)d.chunk, d.n);
     double s = 0.0, m = 0.0;
-    for (int64_t i = a + threadIdx.x; i < b; i += BLOCK) {
-        double v = load_x(d.x, d.dtype, i) - mean;
-        s = fma(v, v, s);
-        m = fmax(m, fabs(v));
+    for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += (int64_t)BLOCK * kMomentUnroll) {
+        double v[kMomentUnroll];
+#pragma unroll
+        for (int u = 0; u < kMomentUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * BLOCK;
+            v[u] = i < b ? load_x(d.x, d.dtype, i) - mean : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kMomentUnroll; ++u) {
+            s = fma(v[u], v[u], s);
+            m = fmax(m, fabs(v[u]));
+        }
     }
     *out_ssq = block_sum<BLOCK>(s, red);
     *out_max = block_max<BLOCK>(m, red);
 }
 
 // ---------------------------------------------------- FP32 pair evaluation
-// Largest |Z| kept by the clamped variant: exp2(-k Z) is exactly 0 there and
-// Z^3 stays finite.
-constexpr float kZClamp = 1.0e12f;
+// Largest Y kept by the clamped variant: exp2(-k Y) is exactly 0 there and
+// Y^3 stays finite.
+constexpr float kYClamp = 1.0e12f;
+// Terms an FP32 accumulator takes before it is added into the FP64 lane sum.
+constexpr int kFold = 4;
+
+template <int RO, bool SAFE, bool EXACT_K>
+__device__ __forceinline__ float pair_poly_exp(float vi, float vj, const PolyConsts& pc, float* e_out) {
+    const float d = vi - vj;
+    float Y = d * d;
+    if (SAFE) Y = fminf(Y, kYClamp);
+    const float a = EXACT_K ? fmaf(Y, pc.k_hi, Y * pc.k_lo) : Y * pc.k_hi;
+    *e_out = __builtin_amdgcn_exp2f(-a);
+    float p;
+    if (RO == 6) {
+        float q = Y - 15.0f;
+        q = fmaf(q, Y, 45.0f);
+        p = fmaf(q, Y, -15.0f);
+    } else {
+        const float q = Y - 6.0f;
+        p = fmaf(q, Y, 3.0f);
+    }
+    return p;
+}
 
 template <int RO, bool SAFE, bool EXACT_K>
 __device__ __forceinline__ float pair_term_f32(float vi, float vj, const PolyConsts& pc) {
-    const float d = vi - vj;
-    float Z = fmaf(d, d, RO == 6 ? -5.0f : -3.0f);
-    if (SAFE) Z = fminf(Z, kZClamp);
-    const float a = EXACT_K ? fmaf(Z, pc.k_hi, Z * pc.k_lo) : Z * pc.k_hi;
-    const float e = __builtin_amdgcn_exp2f(-a);
-    float p;
-    if (RO == 6) {
-        const float q = fmaf(Z, Z, -30.0f);
-        p = fmaf(q, Z, -40.0f);
-    } else {
-        p = fmaf(Z, Z, -6.0f);
-    }
+    float e;
+    const float p = pair_poly_exp<RO, SAFE, EXACT_K>(vi, vj, pc, &e);
     return p * e;
 }
 
 template <int RO, bool SAFE, bool EXACT_K>
 __device__ __forceinline__ void pair_acc_f32(float vi, float vj, float& acc, const PolyConsts& pc) {
-    const float d = vi - vj;
-    float Z = fmaf(d, d, RO == 6 ? -5.0f : -3.0f);
-    if (SAFE) Z = fminf(Z, kZClamp);
-    const float a = EXACT_K ? fmaf(Z, pc.k_hi, Z * pc.k_lo) : Z * pc.k_hi;
-    const float e = __builtin_amdgcn_exp2f(-a);
-    float p;
-    if (RO == 6) {
-        const float q = fmaf(Z, Z, -30.0f);
-        p = fmaf(q, Z, -40.0f);
-    } else {
-        p = fmaf(Z, Z, -6.0f);
-    }
+    float e;
+    const float p = pair_poly_exp<RO, SAFE, EXACT_K>(vi, vj, pc, &e);
     acc = fmaf(p, e, acc);
 }
 
-template <int R>
-__device__ __forceinline__ void kahan_fold(float (&acc)[R][2], float (&ks)[R], float (&kc)[R]) {
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const float chunk = acc[k][0] + acc[k][1];
-        acc[k][0] = 0.0f;
-        acc[k][1] = 0.0f;
-        const float y = chunk - kc[k];
-        const float t = ks[k] + y;
-        kc[k] = (t - ks[k]) - y;
-        ks[k] = t;
-    }
-}
-
 template <int RO, bool SAFE, bool EXACT_K, int R>
-__device__ __forceinline__ void pair_b128_f32(const float (&ui)[R], float4 v, float (&acc)[R][2],
+__device__ __forceinline__ void pair_b128_f32(const float (&ui)[R], float4 v, float (&acc)[R][4],
                                               const PolyConsts& pc) {
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], v.x, acc[k][0], pc);
         pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], v.y, acc[k][1], pc);
-        pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], v.z, acc[k][0], pc);
-        pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], v.w, acc[k][1], pc);
+        pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], v.z, acc[k][2], pc);
+        pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], v.w, acc[k][3], pc);
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void fold_f64(float (&acc)[R][4], double (&tot)[R]) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        tot[k] += ((double)acc[k][0] + (double)acc[k][1]) + ((double)acc[k][2] + (double)acc[k][3]);
+        acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.0f;
     }
 }
 
@@ -274,11 +294,12 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
         const int64_t i = wlo + lane + (int64_t)WAVE * k;
         ui[k] = i < n ? (float)((load_x(d.x, d.dtype, i) - mean) * scale - tau) : 0.0f;
     }
-    float acc[R][2], ks[R], kc[R];
+    float acc[R][4];
+    double tot[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        acc[k][0] = acc[k][1] = 0.0f;
-        ks[k] = kc[k] = 0.0f;
+        acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.0f;
+        tot[k] = 0.0;
     }
 
     const int64_t c0 = r0 + (int64_t)cb * d.W;
@@ -298,7 +319,7 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
             for (int k = 0; k < R; ++k) {
                 const float t = pair_term_f32<RO, SAFE, EXACT_K>(ui[k], uj, pc);
                 const bool live = j > wlo + lane + (int64_t)WAVE * k;
-                acc[k][0] += live ? t : 0.0f;
+                tot[k] += live ? (double)t : 0.0;
             }
         }
         // columns right of this wave's rows: every pair counts
@@ -306,23 +327,23 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
         if (ua < cj + len) {
             int jj = (int)(ua - cj);
             const float4* t4 = reinterpret_cast<const float4*>(tile);
-            for (; jj + 64 <= len; jj += 64) {
+            for (; jj + 4 * kFold <= len; jj += 4 * kFold) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) pair_b128_f32<RO, SAFE, EXACT_K, R>(ui, t4[(jj >> 2) + q], acc, pc);
-                kahan_fold<R>(acc, ks, kc);
+                for (int q = 0; q < kFold; ++q) pair_b128_f32<RO, SAFE, EXACT_K, R>(ui, t4[(jj >> 2) + q], acc, pc);
+                fold_f64<R>(acc, tot);
             }
             for (; jj + 4 <= len; jj += 4) pair_b128_f32<RO, SAFE, EXACT_K, R>(ui, t4[jj >> 2], acc, pc);
+            fold_f64<R>(acc, tot);
             for (; jj < len; ++jj) {
                 const float uj = tile[jj];
 #pragma unroll
-                for (int k = 0; k < R; ++k) pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], uj, acc[k][0], pc);
+                for (int k = 0; k < R; ++k) tot[k] += (double)pair_term_f32<RO, SAFE, EXACT_K>(ui[k], uj, pc);
             }
         }
-        kahan_fold<R>(acc, ks, kc);
     }
     double lane_tot = 0.0;
 #pragma unroll
-    for (int k = 0; k < R; ++k) lane_tot += (double)ks[k] - (double)kc[k];
+    for (int k = 0; k < R; ++k) lane_tot += tot[k];
     return block_sum<BLOCK>(lane_tot, red);
 }
 
@@ -439,7 +460,7 @@ __device__ void finalize_stage(const View& d, State* st, int32_t stage, double t
         break;
     }
     case ST_PSI6: {
-        const double S6 = PREC == 2 ? pc.f6x * tot : PREC == 1 ? pc.f6 * tot : tot / rt2pi;
+        const double S6 = tot / rt2pi;
         st_f64(&st->S6, S6);
         const double A6 = 2.0 * S6 + nd * K6_0;
         const double g1 = d.mode == MODE_PLUGIN ? ld_f64(&st->g1) : d.psi_g;
@@ -456,7 +477,7 @@ __device__ void finalize_stage(const View& d, State* st, int32_t stage, double t
         break;
     }
     case ST_PSI4: {
-        const double S4 = PREC == 2 ? pc.f4x * tot : PREC == 1 ? pc.f4 * tot : tot / rt2pi;
+        const double S4 = tot / rt2pi;
         st_f64(&st->S4, S4);
         const double A4 = 2.0 * S4 + nd * K4_0;
         const double g2 = d.mode == MODE_PLUGIN ? ld_f64(&st->g2) : d.psi_g;
@@ -482,6 +503,13 @@ __global__ void k_init(State* states, int32_t count, uint32_t* ticket) {
     if (i == 0) *ticket = 0u;
 }
 
+// Memory-model cost on a multi-XCD device: an agent-scope release writes
+// back the XCD's L2 and an agent-scope acquire invalidates it, for every CU of
+// that XCD.  The loop therefore (i) fetches the next ticket with a relaxed
+// atomic one item ahead, (ii) waits with relaxed polling and issues one
+// acquire per (block, sample, stage) it has not seen published yet, caching
+// the published scalars in LDS, and (iii) completes an item with a single
+// release read-modify-write; only a stage's finaliser acquires the slots.
 template <int PREC, int R, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
     using TileT = typename std::conditional<PREC >= 1, float, double>::type;
@@ -489,14 +517,23 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
     __shared__ double red[BLOCK / WAVE];
     __shared__ uint32_t sh_ticket;
     __shared__ int32_t sh_status, sh_safe, sh_last;
+    __shared__ int32_t sh_cds, sh_cwait;  // (sample, stage) whose published scalars are cached
     __shared__ double sh_mean, sh_scale;
 
     const int tid = threadIdx.x;
+    uint32_t next = 0;  // thread 0: prefetched ticket
+    if (tid == 0) {
+        next = atomicAdd(A.ticket, 1u);
+        sh_cds = -1;
+        sh_cwait = -1;
+    }
     for (;;) {
-        if (tid == 0) sh_ticket = atomicAdd(A.ticket, 1u);
+        if (tid == 0) {
+            sh_ticket = next;
+            if (next < A.n_items) next = atomicAdd(A.ticket, 1u);
+        }
         __syncthreads();
         const uint32_t t = sh_ticket;
-        __syncthreads();
         if (t >= A.n_items) break;
 
         const Item it = A.items[t];
@@ -504,25 +541,31 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         State* st = A.states + it.ds;
 
         if (tid == 0) {
-            if (it.wait >= 0) {
-                const uint64_t t0 = wall_clock64();
-                while (ld_acquire(&st->ready[it.wait]) == 0u) {
-                    __builtin_amdgcn_s_sleep(8);
-                    if (ld_i32(&st->status) == KDE_ETIMEOUT) break;  // an earlier wait gave up
-                    if (wall_clock64() - t0 > A.timeout_ticks) {
-                        set_status(st, KDE_ETIMEOUT);
-                        break;
-                    }
-                }
-            }
             if (it.stage == ST_SUM && it.a == 0) {
                 __hip_atomic_store(&st->t_first, (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
-            sh_status = ld_i32(&st->status);
-            sh_mean = ld_f64(&st->mean);
-            sh_scale = ld_f64(&st->scale);
-            sh_safe = __hip_atomic_load(&st->safe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (it.wait < 0) {
+                sh_status = ld_i32(&st->status);
+            } else if (sh_cds != it.ds || sh_cwait != it.wait) {
+                const uint64_t t0 = wall_clock64();
+                bool ready = true;
+                while (__hip_atomic_load(&st->ready[it.wait], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                    __builtin_amdgcn_s_sleep(8);
+                    if (ld_i32(&st->status) == KDE_ETIMEOUT || wall_clock64() - t0 > A.timeout_ticks) {
+                        set_status(st, KDE_ETIMEOUT);  // keeps an earlier status if one is set
+                        ready = false;
+                        break;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                sh_status = ld_i32(&st->status);
+                sh_mean = ld_f64(&st->mean);
+                sh_scale = ld_f64(&st->scale);
+                sh_safe = __hip_atomic_load(&st->safe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sh_cds = ready ? it.ds : -1;
+                sh_cwait = ready ? it.wait : -1;
+            }
         }
         __syncthreads();
         const int32_t status = sh_status;
@@ -567,8 +610,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
             s.v = v;
             s.aux = aux;
             A.slots[it.slot] = s;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const uint32_t old = __hip_atomic_fetch_add(&st->done[it.stage], 1u, __ATOMIC_ACQ_REL,
+            const uint32_t old = __hip_atomic_fetch_add(&st->done[it.stage], 1u, __ATOMIC_RELEASE,
                                                         __HIP_MEMORY_SCOPE_AGENT);
             sh_last = (old + 1u == (uint32_t)d.cnt) ? 1 : 0;
         }
@@ -577,13 +619,24 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const int64_t base = d.base;
             const int32_t cnt = d.cnt;
+            // each thread sums its slots k = tid + BLOCK q in q order (Neumaier),
+            // loading U of them at a time so the loads overlap
+            constexpr int U = 8;
             double s = 0.0, c = 0.0, m = 0.0;
-            for (int32_t k = tid; k < cnt; k += BLOCK) {
-                const Slot sl = A.slots[base + k];
-                const double tt = s + sl.v;  // Neumaier step in slot order
-                c += fabs(s) >= fabs(sl.v) ? (s - tt) + sl.v : (sl.v - tt) + s;
-                s = tt;
-                m = fmax(m, sl.aux);
+            for (int32_t k0 = tid; k0 < cnt; k0 += BLOCK * U) {
+                Slot buf[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t k = k0 + u * BLOCK;
+                    buf[u] = k < cnt ? A.slots[base + k] : Slot{0.0, 0.0};
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double tt = s + buf[u].v;
+                    c += fabs(s) >= fabs(buf[u].v) ? (s - tt) + buf[u].v : (buf[u].v - tt) + s;
+                    s = tt;
+                    m = fmax(m, buf[u].aux);
+                }
             }
             const double tot = block_sum<BLOCK>(s + c, red);
             const double mx = block_max<BLOCK>(m, red);

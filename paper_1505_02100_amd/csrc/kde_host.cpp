@@ -55,7 +55,7 @@ int hip_fail(hipError_t e, const char* what) {
 
 const double kPi = 3.14159265358979323846;
 constexpr int kBlock = 256;           // threads per block of the persistent kernel
-constexpr int64_t kMomentChunk = 65536;
+constexpr int64_t kMomentChunk = 8192;  // elements per moment item (32 per thread)
 constexpr int64_t kDefaultTarget = 16384;
 constexpr uint64_t kTimeoutTicks = 20ull * 100000000ull;  // 20 s at the 100 MHz wall clock
 
@@ -86,16 +86,9 @@ struct DevBuf {
 PolyConsts make_consts() {
     // exp(-y^2/2) = 2^(-k y^2) with k = log2(e)/2 (see kde_device.hip)
     const double k = 0.5 / std::log(2.0);
-    const double rt2pi = std::sqrt(2.0 * kPi);
     PolyConsts pc{};
     pc.k_hi = (float)k;
     pc.k_lo = (float)(k - (double)pc.k_hi);
-    const double kx = (double)pc.k_hi + (double)pc.k_lo;
-    // e = exp2(-k Z) with Z = y^2 - 5 (r = 6) or y^2 - 3 (r = 4)
-    pc.f6 = std::exp2(-5.0 * (double)pc.k_hi) / rt2pi;
-    pc.f4 = std::exp2(-3.0 * (double)pc.k_hi) / rt2pi;
-    pc.f6x = std::exp2(-5.0 * kx) / rt2pi;
-    pc.f4x = std::exp2(-3.0 * kx) / rt2pi;
     return pc;
 }
 
@@ -194,7 +187,8 @@ struct SampleSpec {
 };
 
 int64_t moment_chunk(int64_t n) {
-    return std::max<int64_t>(kMomentChunk, (n + 1023) / 1024);
+    // at most 4096 moment items per sample
+    return std::max<int64_t>(kMomentChunk, (n + 4095) / 4096);
 }
 
 // Build the ordered work list: stage-major over samples (largest first), so

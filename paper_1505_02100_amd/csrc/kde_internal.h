@@ -72,15 +72,10 @@ struct Slot {
     double aux;  // moments pass 2: max |x - mean|; otherwise 0
 };
 
-// Constants of the FP32 pair evaluation (derivation in kde_device.hip) and
-// the FP64 factors that turn its sums into sums of K6 and K4.
+// Constants of the FP32 pair evaluation (derivation in kde_device.hip).
 struct PolyConsts {
     float k_hi;    // log2(e)/2 rounded to FP32
     float k_lo;    // log2(e)/2 - k_hi rounded to FP32 (exact-k variant)
-    double f6;     // sum K6 = f6 * sum p e  with e = exp2(-k_hi Z)
-    double f4;     // sum K4 = f4 * sum p e
-    double f6x;    // the same with the two-term k
-    double f4x;
 };
 
 // Arguments of the persistent kernel.
