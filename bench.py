@@ -1,0 +1,198 @@
+"""Benchmark of the PLUGIN bandwidth selector's hot path on one MI355X.
+
+One step = one complete bandwidth selection (Algorithm 1, Steps I-VII: the
+moment reduction, the Step IV and Step VI pair sums over all n(n-1)/2 pairs
+each, and the scalar stages) for one sample already resident in HBM, through
+the C ABI (kde_plugin_bandwidth_ex on a device pointer).  The default
+workload is the single-dataset configuration: n = 65536 draws from the
+bimodal mixture 0.5 N(-1, (2/3)^2) + 0.5 N(1, (2/3)^2), seed 1, FP32 pair
+arithmetic with compensated sums (FP64 plain is timed beside it).
+
+value      = pair evaluations per second, n(n-1) per selection (the diagonal is
+             added analytically and not counted)
+roofline   = the persistent kernel's algorithmic FP32 FLOP rate (10 FLOP per
+             pair at r = 6, 8 at r = 4; FMA = 2, exp2 = 1) against the FP32
+             vector peak of 157.3 TFLOP/s; its duration comes from HIP events
+             recorded by the library on the launch stream around every launch
+cpu_baseline = the FP64 oracle (plain C + OpenMP, all host cores) on the same
+             sample, one full selection
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp32x|fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3      # MI355X datasheet, packed FP32 vector
+FP32_NONPACKED_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+FLOP_PER_PAIR = {6: 10, 4: 8}
+
+WORKLOADS = {
+    "normal1024": dict(desc="single dataset n=1024, N(0,1), seed 0", n=1024, kind="normal", seed=0),
+    "bimodal65536": dict(desc="single dataset n=65536, 0.5N(-1,(2/3)^2)+0.5N(1,(2/3)^2), seed 1",
+                         n=65536, kind="bimodal", seed=1),
+    "lognormal1m": dict(desc="single dataset n=2^20, 1e3*exp(Z)-5e2, Z~N(0,1), seed 2",
+                        n=1 << 20, kind="lognormal", seed=2),
+}
+
+
+def make_sample(w):
+    from paper_1505_02100_amd import synth
+    if w["kind"] == "normal":
+        return synth.workload_single_normal(w["n"], w["seed"])
+    if w["kind"] == "bimodal":
+        return synth.workload_single_bimodal(w["n"], w["seed"])
+    return synth.workload_single_lognormal(w["n"], w["seed"])
+
+
+def kernel_source_sha256():
+    p = os.path.join(ROOT, "paper_1505_02100_amd", "csrc", "kde_device.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the persistent kernel from the committed
+    rocprofv3 counter summary, or None if absent or taken on other code."""
+    p = os.path.join(ROOT, "profiles", f"traffic_k_persistent_{workload}_{precision}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def calib_copy(steps):
+    """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    nbytes = 256 << 20
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read": nbytes, "calib_copy_bytes_written": nbytes,
+                      "launches": steps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", choices=["fp32", "fp32x", "fp64"], default="fp32")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="bimodal65536")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run only a 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE {world}); multi-GPU sharding is described in DESIGN.md but not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    if args.calib_copy:
+        calib_copy(args.steps)
+        return
+
+    from paper_1505_02100_amd import kdeplugin as kp
+
+    prec_code = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT,
+                 "fp64": kp.KDE_FP64_PLAIN}[args.precision]
+    w = WORKLOADS[args.workload]
+    x = make_sample(w)
+    n = x.size
+    pairs = n * (n - 1)             # pair evaluations per selection (both Psi stages)
+    flop = sum(FLOP_PER_PAIR.values()) * (n * (n - 1) // 2)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    torch.cuda.synchronize()
+
+    ctx = kp.Context(prec_code)
+    for _ in range(max(1, args.warmup)):
+        ctx.plugin_bandwidth(xd)
+    torch.cuda.synchronize()
+    dev_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = ctx.plugin_bandwidth(xd)
+        dev_ms.append(ctx.last_device_ms())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = pairs / ((t1 - t0) / args.steps)
+    timeline = ctx.last_timeline(0)
+    cfg = ctx.config()
+    dev_ms_avg = float(np.mean(dev_ms))
+
+    achieved = flop / (dev_ms_avg * 1e-3) / 1e12
+    traffic = measured_traffic(args.workload, args.precision)
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": traffic,
+                "kernel": "kde::k_persistent", "kernel_ms_avg": round(dev_ms_avg, 4),
+                "flop_per_launch": flop,
+                "frac_of_nonpacked_fp32": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4)}
+
+    out = {"metric": "pair-evals/s & %FP32 VALU peak; selections/s, p50/p99 latency vs FP64 plain",
+           "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+           "config": {"workload": w["desc"] + ", Steps I-VII per step, samples resident in HBM",
+                      "n": n, "precision": args.precision, "pairs_per_selection": pairs,
+                      "tile": cfg},
+           "selections_per_s": round(1e3 / ms_per_step, 3),
+           "stage_timeline_ms": [round(t, 4) for t in timeline],
+           "roofline": roofline}
+
+    if not args.no_fp64_compare and args.precision != "fp64":
+        ctx64 = kp.Context(kp.KDE_FP64_PLAIN)
+        ctx64.plugin_bandwidth(xd)
+        k64 = max(3, args.steps // 10)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(k64):
+            r64 = ctx64.plugin_bandwidth(xd)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        out["fp64_plain"] = {"pair_evals_per_s": pairs / ((b - a) / k64),
+                             "selections_per_s": round(k64 / (b - a), 3),
+                             "ms_per_step": round((b - a) * 1e3 / k64, 4),
+                             "speedup_of_measured_path": round(value / (pairs / ((b - a) / k64)), 3),
+                             "rel_diff_h": abs(res.h - r64.h) / r64.h}
+        ctx64.close()
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.num_threads()
+        a = time.perf_counter()
+        ref = oracle.plugin(x)
+        b = time.perf_counter()
+        out["cpu_baseline"] = {"value": pairs / (b - a), "unit": "pair-evals/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"one full selection of the same n={n} sample "
+                                         f"({pairs} pair evaluations, {b - a:.2f} s)"}
+        out["rel_err_vs_oracle"] = {k: abs(getattr(res, k) - getattr(ref, k)) / abs(getattr(ref, k))
+                                    for k in ("h", "psi6", "psi4", "g2")}
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -130,6 +130,11 @@ void kde_ctx_destroy(kde_ctx* ctx);
 int kde_ctx_config(const kde_ctx* ctx, int32_t* rows_per_lane, int32_t* block_threads,
                    int32_t* tile_rows, int32_t* blocks_per_cu);
 
+/* Device time in milliseconds of the last synchronous call's launch on this
+ * context (init kernel + persistent kernel), measured with HIP events
+ * recorded on the caller's stream around the launch; -1 if none yet. */
+double kde_ctx_last_device_ms(const kde_ctx* ctx);
+
 /* Device timeline of sample `sample` of the last synchronous call on this
  * context: ms[k] = milliseconds from the start of the sample's first work
  * item to the moment stage k published its result (k = 0: mean, 1: sigma

@@ -117,6 +117,8 @@ struct Plan {
 
 struct kde_ctx {
     std::vector<State> last_states;           // device state records of the last call
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket each launch on the caller's stream
+    double last_device_ms = -1.0;             // init + persistent kernel time of the last call
     int device = 0;
     int precision = KDE_FP64_PLAIN;
     int64_t mem_budget = 0;
@@ -343,7 +345,9 @@ int run_plan(kde_ctx* c, Plan& p, hipStream_t s) {
             return hip_fail(e, "graph capture of the persistent kernel");
         }
     }
+    HIPCHK(hipEventRecord(c->ev0, s));
     HIPCHK(hipGraphLaunch(p.exec, s));
+    HIPCHK(hipEventRecord(c->ev1, s));
     return KDE_OK;
 }
 
@@ -428,6 +432,8 @@ int finish(kde_ctx* c, Plan& p, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(p.h_states, p.d_states.p, sizeof(State) * p.count, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     c->last_states.assign(p.h_states, p.h_states + p.count);
+    float ms = -1.0f;
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_device_ms = ms;
     return KDE_OK;
 }
 
@@ -540,6 +546,8 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, c->device));
     c->cus = prop.multiProcessorCount;
+    HIPCHK(hipEventCreate(&c->ev0));
+    HIPCHK(hipEventCreate(&c->ev1));
     int occ = 0;
     HIPCHK(persistent_occupancy(c->precision, c->R, &occ));
     c->blocks_per_cu = o.blocks_per_cu ? o.blocks_per_cu : std::max(1, occ);
@@ -551,6 +559,8 @@ void kde_ctx_destroy(kde_ctx* ctx) {
     if (!ctx) return;
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
 }
 
@@ -695,6 +705,14 @@ int kde_plugin_bandwidth_batch(kde_ctx* c, const void* const* xs, const int64_t*
         if (out[valid[q]].status) out[valid[q]].h = NAN;
     }
     return ok();
+}
+
+double kde_ctx_last_device_ms(const kde_ctx* c) {
+    if (!c) {
+        set_err(KDE_EINVAL, "null context");
+        return -1.0;
+    }
+    return c->last_device_ms;
 }
 
 int kde_ctx_last_timeline(const kde_ctx* c, int64_t sample, double* ms) {

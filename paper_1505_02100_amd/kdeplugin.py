@@ -120,6 +120,7 @@ _sig("kde_plugin_bandwidth_ex", ctypes.c_int, _P, _P, _I64, ctypes.c_int, ctypes
 _sig("kde_plugin_bandwidth_batch", ctypes.c_int, _P, ctypes.POINTER(_P), _PI64, _I64, ctypes.c_int,
      ctypes.POINTER(kde_result), _P)
 _sig("kde_ctx_last_timeline", ctypes.c_int, _P, _I64, ctypes.POINTER(_D))
+_sig("kde_ctx_last_device_ms", _D, _P)
 _sig("kde_psi_num_items", _I64, _P, _I64)
 _sig("kde_psi_item_geometry", ctypes.c_int, _P, _I64, _I64, _PI64, _PI64, _PI64, _PI64)
 _sig("kde_psi_range", ctypes.c_int, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D,
@@ -250,6 +251,11 @@ def kde_ctx_last_timeline(ctx: int, sample: int = 0) -> List[float]:
     return list(ms)
 
 
+def kde_ctx_last_device_ms(ctx: int) -> float:
+    """Device time (ms) of the last call's launch, from HIP events on its stream."""
+    return _lib.kde_ctx_last_device_ms(ctx)
+
+
 def kde_psi_ex(ctx: int, x, r: int, g: float) -> float:
     s = _Samples(x)
     out = _D()
@@ -336,6 +342,9 @@ class Context:
 
     def last_timeline(self, sample: int = 0):
         return kde_ctx_last_timeline(self.handle, sample)
+
+    def last_device_ms(self):
+        return kde_ctx_last_device_ms(self.handle)
 
     def psi(self, x, r, g):
         return kde_psi_ex(self.handle, x, r, g)
