@@ -85,13 +85,93 @@ def calib_copy(steps):
                       "launches": steps}))
 
 
+def bench_batch(args):
+    """512 samples, n log-uniform in [256, 65536], normal / bimodal / t3 mixed:
+    one call = one persistent launch over all of them (graph replay), against
+    512 sequential single-sample calls (FP64 plain and the measured precision)."""
+    import numpy as np
+    import tempfile
+    import torch
+    from paper_1505_02100_amd import kdeplugin as kp
+    from paper_1505_02100_amd import synth
+    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp64": kp.KDE_FP64_PLAIN}
+    xs, names = synth.workload_batch(512, 3)
+    xds = [torch.from_numpy(x).cuda() for x in xs]
+    pairs = sum(x.size * (x.size - 1) for x in xs)
+    torch.cuda.synchronize()
+    table = args.tune_table
+    tuned = None
+    if not table:
+        table = os.path.join(tempfile.gettempdir(), f"kde_tune_{args.precision}.json")
+        t0 = time.perf_counter()
+        tuned = kp.kde_autotune(prec[args.precision], [x.size for x in xs], table,
+                                mode=kp.KDE_TUNE_BATCH, reps=3)
+        tuned["seconds"] = round(time.perf_counter() - t0, 2)
+    ctx = kp.Context(prec[args.precision], tune_table=table)
+    ctx.plugin_bandwidth_batch(xds)
+    torch.cuda.synchronize()
+    dev = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = ctx.plugin_bandwidth_batch(xds)
+        dev.append(ctx.last_device_ms())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = (t1 - t0) / args.steps
+    dev_ms = float(np.mean(dev))
+    flop = sum(FLOP_PER_PAIR.values()) * sum(x.size * (x.size - 1) // 2 for x in xs)
+    achieved = flop / (dev_ms * 1e-3) / 1e12
+
+    def sequential(p, tt=None):
+        c = kp.Context(p, tune_table=tt) if tt else kp.Context(p)
+        for xd in xds[:4]:
+            c.plugin_bandwidth(xd)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        hs = [c.plugin_bandwidth(xd).h for xd in xds]
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        c.close()
+        return b - a, hs
+
+    seq64_s, h64 = sequential(kp.KDE_FP64_PLAIN)
+    seq_s, hseq = sequential(prec[args.precision], table)
+    worst64 = max(abs(r.h - h) / h for r, h in zip(res, h64))
+    same = all(r.h == h for r, h in zip(res, hseq))
+    out = {"metric": "pair-evals/s & %FP32 VALU peak; selections/s, p50/p99 latency vs FP64 plain",
+           "value": pairs / per, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 1, "ms_per_step": round(per * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+           "config": {"workload": "batch of 512 samples, n log-uniform in [256, 65536], N(0,1) / bimodal / t3 "
+                                  "with equal probability, one persistent launch per batch (graph replay)",
+                      "samples": len(xs), "sum_n": int(sum(x.size for x in xs)),
+                      "pairs_per_batch": int(pairs), "precision": args.precision,
+                      "tile": ctx.config(), "tune_table": tuned},
+           "selections_per_s": round(len(xs) / per, 1),
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                        "traffic": None, "kernel": "kde::k_persistent", "kernel_ms_avg": round(dev_ms, 4)},
+           "sequential_fp64_plain": {"seconds": round(seq64_s, 4),
+                                     "selections_per_s": round(len(xs) / seq64_s, 1),
+                                     "speedup_of_batch": round(seq64_s / per, 2),
+                                     "max_rel_diff_h": worst64},
+           "sequential_same_precision": {"seconds": round(seq_s, 4),
+                                         "selections_per_s": round(len(xs) / seq_s, 1),
+                                         "speedup_of_batch": round(seq_s / per, 2),
+                                         "bitwise_equal_h": same}}
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["fp32", "fp32x", "fp64"], default="fp32")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="bimodal65536")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch512"], default="bimodal65536")
+    ap.add_argument("--tune-table", default=None, help="autotune table for the batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -109,6 +189,10 @@ def main():
     import torch
     if args.calib_copy:
         calib_copy(args.steps)
+        return
+
+    if args.workload == "batch512":
+        bench_batch(args)
         return
 
     from paper_1505_02100_amd import kdeplugin as kp

@@ -196,6 +196,28 @@ int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtyp
                   double g, int64_t item_begin, int64_t item_end, kde_stream stream,
                   double* partial);
 
+/* ------------------------------------------------------------- autotuner */
+
+/* Search the tile configuration for opt->precision on opt->device (opt may
+ * be NULL for the defaults): rows per lane R in {1, 2, 4} (tile height 256 R),
+ * persistent blocks per CU (occupancy limit and one below) and the size of
+ * the pair items.  Each candidate is timed with HIP events on the launch
+ * stream (median of reps launches) on synthetic normal samples with the
+ * sizes ns[0..count):
+ *   mode KDE_TUNE_SINGLE: every size alone, one selection per launch; the
+ *     (R, blocks per CU) with the least total time wins, with the best item
+ *     count per size (table key "targets");
+ *   mode KDE_TUNE_BATCH: all samples in one kde_plugin_bandwidth_batch
+ *     launch; items are sized to a pair budget B (table key "pair_budget").
+ * The table is written to out_path as JSON and read back through
+ * kde_options.tune_table.  None of these parameters changes what is
+ * computed; for a given table results are deterministic.  verbose != 0
+ * prints every timing to stderr.  Synchronous. */
+#define KDE_TUNE_SINGLE 0
+#define KDE_TUNE_BATCH 1
+int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t count, int32_t mode,
+                 int32_t reps, const char* out_path, int32_t verbose);
+
 #ifdef __cplusplus
 }
 #endif

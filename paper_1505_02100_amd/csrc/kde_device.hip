@@ -22,7 +22,10 @@
 //     d = vi - vj; Y = d d; a = k Y; e = exp2(-a);
 //     q = Y - 15; q = fma(q, Y, 45); p = fma(q, Y, -15); acc = fma(p, e, acc)
 // which is 7 VALU + 1 transcendental (r = 4 drops one fma: 6 + 1); 1/sqrt(2 pi)
-// is applied once to the FP64 total.
+// is applied once to the FP64 total.  The default precision evaluates Step IV
+// in the depressed form instead (Z = Y - 5, He6 = (Z^2 - 30) Z - 40, 6 + 1):
+// h depends on Psi6 only through g2^(1/7) and Psi4's weak dependence on g2,
+// so the small absorption bias of that form costs about 1e-8 in h.
 //
 // Why this form.  The sums of K6 and K4 over all pairs cancel heavily:
 // sum |K| / |sum K| is in the hundreds at n = 1024 and grows like g^-6, to
@@ -220,11 +223,24 @@ constexpr int kFold = 4;
 template <int RO, bool SAFE, bool EXACT_K>
 __device__ __forceinline__ float pair_poly_exp(float vi, float vj, const PolyConsts& pc, float* e_out) {
     const float d = vi - vj;
+    float p;
+    if (RO == 6 && !EXACT_K) {
+        // Step IV, default precision: the depressed form Z = Y - 5,
+        // He6 = (Z^2 - 30) Z - 40 and exp(-Y/2) = 2^(-k Z) 2^(-5k), one VALU op
+        // less per pair.  Its absorption of a tiny Y into -5 biases Psi6 by a
+        // few 1e-6 at n = 2^20, which reaches h only through g2^(1/7) and
+        // Psi4's weak dependence on g2 (about 1e-8 in h).
+        float Z = fmaf(d, d, -5.0f);
+        if (SAFE) Z = fminf(Z, kYClamp);
+        *e_out = __builtin_amdgcn_exp2f(-(Z * pc.k_hi));
+        const float q = fmaf(Z, Z, -30.0f);
+        p = fmaf(q, Z, -40.0f);
+        return p;
+    }
     float Y = d * d;
     if (SAFE) Y = fminf(Y, kYClamp);
     const float a = EXACT_K ? fmaf(Y, pc.k_hi, Y * pc.k_lo) : Y * pc.k_hi;
     *e_out = __builtin_amdgcn_exp2f(-a);
-    float p;
     if (RO == 6) {
         float q = Y - 15.0f;
         q = fmaf(q, Y, 45.0f);
@@ -271,6 +287,20 @@ __device__ __forceinline__ void fold_f64(float (&acc)[R][4], double (&tot)[R]) {
     }
 }
 
+// Columns of pair item cb of the row block starting at row r0: the row
+// block's L = n - r0 columns (its part of the upper triangle) are cut into
+// m = ceil(L / W) chunks of equal width, rounded up to a multiple of 4 (the
+// b128 column reads need 16-byte alignment).  The host enumerates items with
+// the same arithmetic.
+__device__ __forceinline__ void item_columns(int64_t n, int64_t r0, int64_t W, int32_t cb,
+                                             int64_t* c0, int64_t* c1) {
+    const int64_t L = n - r0;
+    const int64_t m = (L + W - 1) / W;
+    const int64_t w = (((L + m - 1) / m) + 3) & ~(int64_t)3;
+    *c0 = r0 + (int64_t)cb * w;
+    *c1 = min(*c0 + w, n);
+}
+
 // Generic centring offset of row block rb (see the header comment).
 __device__ __forceinline__ double centre_offset(int32_t rb) {
     const double f = (double)rb * 0.6180339887498949;
@@ -302,8 +332,8 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
         tot[k] = 0.0;
     }
 
-    const int64_t c0 = r0 + (int64_t)cb * d.W;
-    const int64_t c1 = min(c0 + d.W, n);
+    int64_t c0, c1;
+    item_columns(n, r0, d.W, cb, &c0, &c1);
     for (int64_t cj = c0; cj < c1; cj += TJ) {
         const int len = (int)min((int64_t)TJ, c1 - cj);
         __syncthreads();
@@ -377,8 +407,8 @@ __device__ double pair_item_f64(const View& d, int32_t rb, int32_t cb, double me
         ui[k] = i < n ? (load_x(d.x, d.dtype, i) - mean) * scale : 0.0;
         acc[k][0] = acc[k][1] = 0.0;
     }
-    const int64_t c0 = r0 + (int64_t)cb * d.W;
-    const int64_t c1 = min(c0 + d.W, n);
+    int64_t c0, c1;
+    item_columns(n, r0, d.W, cb, &c0, &c1);
     for (int64_t cj = c0; cj < c1; cj += TJ) {
         const int len = (int)min((int64_t)TJ, c1 - cj);
         __syncthreads();
@@ -460,7 +490,8 @@ __device__ void finalize_stage(const View& d, State* st, int32_t stage, double t
         break;
     }
     case ST_PSI6: {
-        const double S6 = tot / rt2pi;
+        // the default FP32 path evaluates Step IV with exp2(-k Z), Z = Y - 5
+        const double S6 = (PREC == 1 ? exp2(-5.0 * (double)pc.k_hi) : 1.0) * tot / rt2pi;
         st_f64(&st->S6, S6);
         const double A6 = 2.0 * S6 + nd * K6_0;
         const double g1 = d.mode == MODE_PLUGIN ? ld_f64(&st->g1) : d.psi_g;

@@ -56,7 +56,6 @@ int hip_fail(hipError_t e, const char* what) {
 const double kPi = 3.14159265358979323846;
 constexpr int kBlock = 256;           // threads per block of the persistent kernel
 constexpr int64_t kMomentChunk = 8192;  // elements per moment item (32 per thread)
-constexpr int64_t kDefaultTarget = 16384;
 constexpr uint64_t kTimeoutTicks = 20ull * 100000000ull;  // 20 s at the 100 MHz wall clock
 
 // ------------------------------------------------------------ device buffer
@@ -124,7 +123,9 @@ struct kde_ctx {
     int64_t mem_budget = 0;
     int R = 1;
     int blocks_per_cu = 0;
-    int64_t target_items = kDefaultTarget;
+    int64_t target_items = 0;                 // 0 = by sample size
+    int64_t bucket_target[64] = {0};          // from a tune table: by floor(log2 n)
+    int64_t pair_budget = 0;                  // from a tune table: pairs per item for every n
     int cus = 0;
     PolyConsts pc{};
     std::list<std::unique_ptr<Plan>> plans;   // most recently used first
@@ -134,6 +135,83 @@ struct kde_ctx {
 };
 
 namespace {
+
+// Pair work items per stage: small samples favour fewer, larger items (less
+// per-item latency), large ones more items (a shorter tail at the end of each
+// stage).  Measured on MI355X for the FP32 kernel with 256-row tiles; a
+// context option or tune table overrides it.
+int64_t target_items_for(const kde_ctx* c, int64_t n) {
+    if (c->target_items > 0) return c->target_items;
+    if (c->pair_budget > 0) {
+        const double P = 0.5 * (double)n * (double)(n - 1);
+        return std::max<int64_t>(1, (int64_t)(P / (double)c->pair_budget));
+    }
+    int lg = 0;
+    while (lg < 62 && ((int64_t)2 << lg) <= n) ++lg;
+    for (int b = lg; b >= 0; --b)
+        if (c->bucket_target[b] > 0) return c->bucket_target[b];
+    return n < (int64_t)1 << 17 ? 8192 : 32768;
+}
+
+// Tune table (written by kde_autotune): a small JSON object
+//   {"precision": p, "rows_per_lane": R, "blocks_per_cu": b,
+//    "targets": [[log2n, items], ...]}          (tuned per sample size), or
+//   {..., "pair_budget": B}                     (tuned for batches)
+// A [log2n, items] entry applies to samples with floor(log2 n) >= log2n up
+// to the next entry; a pair budget sizes every sample's items to about B
+// pairs.
+struct TuneTable {
+    int precision = -1, R = 0, bpc = 0;
+    int64_t bucket[64] = {0};
+    int64_t pair_budget = 0;
+};
+
+bool json_int(const std::string& t, const char* key, long long* v) {
+    const size_t k = t.find(std::string("\"") + key + "\"");
+    if (k == std::string::npos) return false;
+    const size_t c = t.find(':', k);
+    if (c == std::string::npos) return false;
+    char* end = nullptr;
+    *v = std::strtoll(t.c_str() + c + 1, &end, 10);
+    return end != t.c_str() + c + 1;
+}
+
+int load_tune_table(const char* path, TuneTable* tt) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return set_err(KDE_EINVAL, std::string("cannot open tune table ") + path);
+    std::string t;
+    char buf[4096];
+    size_t r;
+    while ((r = std::fread(buf, 1, sizeof buf, f)) > 0) t.append(buf, r);
+    std::fclose(f);
+    long long v;
+    if (json_int(t, "precision", &v)) tt->precision = (int)v;
+    if (json_int(t, "rows_per_lane", &v)) tt->R = (int)v;
+    if (json_int(t, "blocks_per_cu", &v)) tt->bpc = (int)v;
+    if (json_int(t, "pair_budget", &v)) tt->pair_budget = v;
+    const size_t k = t.find("\"targets\"");
+    if (k != std::string::npos) {
+        const size_t open = t.find('[', k);
+        const size_t close = t.find("]]", k);
+        if (open == std::string::npos || close == std::string::npos || close < open)
+            return set_err(KDE_EINVAL, std::string("malformed targets in tune table ") + path);
+        size_t pos = open + 1;
+        while (pos < close) {
+            const size_t lb = t.find('[', pos);
+            if (lb == std::string::npos || lb > close) break;
+            long long lg = -1, items = 0;
+            if (std::sscanf(t.c_str() + lb, "[%lld , %lld]", &lg, &items) != 2)
+                return set_err(KDE_EINVAL, std::string("malformed targets in tune table ") + path);
+            if (lg >= 0 && lg < 64 && items > 0) tt->bucket[lg] = items;
+            pos = t.find(']', lb);
+            if (pos == std::string::npos) break;
+            ++pos;
+        }
+    }
+    if ((tt->R != 0 && tt->R != 1 && tt->R != 2 && tt->R != 4) || tt->bpc < 0 || tt->bpc > 16)
+        return set_err(KDE_EINVAL, std::string("malformed tune table ") + path);
+    return KDE_OK;
+}
 
 // Pair-item decomposition of the strict upper triangle for a sample of size n.
 struct PairGeom {
@@ -146,16 +224,24 @@ PairGeom pair_geom(const kde_ctx* c, int64_t n) {
     g.TI = (int64_t)kBlock * c->R;
     g.RB = (n + g.TI - 1) / g.TI;
     const double P = 0.5 * (double)n * (double)(n - 1);
-    const double want = P / ((double)g.TI * (double)std::max<int64_t>(1, c->target_items));
+    const double want = P / ((double)g.TI * (double)std::max<int64_t>(1, target_items_for(c, n)));
     int64_t W = 64;
     while ((double)W < want && W < ((int64_t)1 << 40)) W <<= 1;
     g.W = W;
     return g;
 }
 
+// Row block rb's columns [rb TI, n) are cut into equal chunks of at most W
+// (rounded up to a multiple of 4); the device computes the same widths.
 int64_t pair_items_in_row(const PairGeom& g, int64_t rb) {
     const int64_t cols = g.n - rb * g.TI;
     return cols > 0 ? (cols + g.W - 1) / g.W : 0;
+}
+
+int64_t pair_chunk_width(const PairGeom& g, int64_t rb) {
+    const int64_t L = g.n - rb * g.TI;
+    const int64_t m = (L + g.W - 1) / g.W;
+    return (((L + m - 1) / m) + 3) & ~(int64_t)3;
 }
 
 int64_t pair_item_count(const PairGeom& g) {
@@ -535,12 +621,21 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev == 0) return set_err(KDE_EDEVICE, "no HIP device available");
     if (o.device < 0 || o.device >= ndev) return set_err(KDE_EINVAL, "device ordinal out of range");
+    TuneTable tt;
+    if (o.tune_table) {
+        const int st = load_tune_table(o.tune_table, &tt);
+        if (st) return st;
+        if (tt.precision >= 0 && tt.precision != o.precision)
+            return set_err(KDE_EINVAL, "tune table was made for another precision");
+    }
     auto c = std::make_unique<kde_ctx>();
+    for (int b = 0; b < 64; ++b) c->bucket_target[b] = tt.bucket[b];
+    c->pair_budget = tt.pair_budget;
     c->device = o.device;
     c->precision = o.precision;
     c->mem_budget = o.mem_budget;
-    c->R = o.rows_per_lane ? o.rows_per_lane : (o.precision != KDE_FP64_PLAIN ? 2 : 1);
-    c->target_items = o.target_items ? o.target_items : kDefaultTarget;
+    c->R = o.rows_per_lane ? o.rows_per_lane : (tt.R ? tt.R : 1);
+    c->target_items = o.target_items;
     c->pc = make_consts();
     DeviceGuard dg(c->device);
     hipDeviceProp_t prop;
@@ -550,7 +645,7 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     HIPCHK(hipEventCreate(&c->ev1));
     int occ = 0;
     HIPCHK(persistent_occupancy(c->precision, c->R, &occ));
-    c->blocks_per_cu = o.blocks_per_cu ? o.blocks_per_cu : std::max(1, occ);
+    c->blocks_per_cu = o.blocks_per_cu ? o.blocks_per_cu : (tt.bpc ? std::min(tt.bpc, std::max(1, occ)) : std::max(1, occ));
     *out = c.release();
     return ok();
 }
@@ -590,11 +685,12 @@ int kde_psi_item_geometry(const kde_ctx* c, int64_t n, int64_t item, int64_t* r0
     int64_t rb, cb;
     if (!pair_item_at(g, item, &rb, &cb)) return set_err(KDE_EINVAL, "item index out of range");
     const int64_t a = rb * g.TI;
-    const int64_t cs = a + cb * g.W;
+    const int64_t w = pair_chunk_width(g, rb);
+    const int64_t cs = a + cb * w;
     if (r0) *r0 = a;
     if (r1) *r1 = std::min(a + g.TI, n);
     if (c0) *c0 = cs;
-    if (c1) *c1 = std::min(cs + g.W, n);
+    if (c1) *c1 = std::min(cs + w, n);
     return ok();
 }
 

@@ -122,6 +122,8 @@ _sig("kde_plugin_bandwidth_batch", ctypes.c_int, _P, ctypes.POINTER(_P), _PI64, 
 _sig("kde_ctx_last_timeline", ctypes.c_int, _P, _I64, ctypes.POINTER(_D))
 _sig("kde_ctx_last_device_ms", _D, _P)
 _sig("kde_psi_num_items", _I64, _P, _I64)
+_sig("kde_autotune", ctypes.c_int, ctypes.POINTER(kde_options), _PI64, _I32, _I32, _I32, ctypes.c_char_p,
+     _I32)
 _sig("kde_psi_item_geometry", ctypes.c_int, _P, _I64, _I64, _PI64, _PI64, _PI64, _PI64)
 _sig("kde_psi_range", ctypes.c_int, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D,
      _I64, _I64, _P, ctypes.POINTER(_D))
@@ -311,6 +313,24 @@ def kde_psi_range(ctx: int, x, r: int, g: float, item_begin: int, item_end: int)
     _check(_lib.kde_psi_range(ctx, s.ptr, s.n, s.mem, s.dtype, int(r), float(g), int(item_begin),
                               int(item_end), s.stream, ctypes.byref(out)), "kde_psi_range")
     return out.value
+
+
+KDE_TUNE_SINGLE = 0
+KDE_TUNE_BATCH = 1
+
+
+def kde_autotune(precision: int, ns: Sequence[int], out_path: str, mode: int = KDE_TUNE_SINGLE,
+                 reps: int = 5, device: int = 0, verbose: bool = False) -> dict:
+    """Run the library's tile-configuration search and return the table."""
+    import json
+    o = kde_options_init()
+    o.device = device
+    o.precision = precision
+    arr = (_I64 * len(ns))(*[int(v) for v in ns])
+    _check(_lib.kde_autotune(ctypes.byref(o), arr, len(ns), int(mode), int(reps), out_path.encode(),
+                             int(verbose)), "kde_autotune")
+    with open(out_path) as f:
+        return json.load(f)
 
 
 class Context:

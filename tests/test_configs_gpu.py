@@ -1,0 +1,133 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times (default context tile shape, one persistent
+launch per call, device-resident samples).
+
+* bimodal n = 65536: full oracle comparison, both precisions.
+* lognormal n = 2^20 (x = 1e3 exp(Z) - 5e2): the O(n^2) oracle would take
+  minutes, so sampled pair items are compared one by one with the oracle's
+  block sums over the same rectangles, and the whole result is checked
+  through properties that hold at any size (scale equivariance, agreement of
+  the FP32 and FP64 paths, sign invariant).
+* batch of 512 samples, n log-uniform in [256, 65536], mixed distributions:
+  every h against the FP64 batch and against the oracle for all samples with
+  n <= 4096 plus a few larger ones; the batch results are bitwise those of
+  single calls.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_02100_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kp():
+    from paper_1505_02100_amd import kdeplugin
+    return kdeplugin
+
+
+@pytest.fixture(scope="module")
+def ctxs(kp):
+    c = {p: kp.Context(p) for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT)}
+    yield c
+    for v in c.values():
+        v.close()
+
+
+def _rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def test_bimodal_65536_full_oracle(kp, ctxs):
+    import torch
+    x = synth.workload_single_bimodal(65536, 1)
+    ref = oracle.plugin(x)
+    xd = torch.from_numpy(x).cuda()
+    r64 = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth(xd)
+    assert _rel(r64.h, ref.h) < 1e-12 and _rel(r64.psi6, ref.psi6) < 1e-12 and _rel(r64.psi4, ref.psi4) < 1e-12
+    for p in (kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT):
+        r = ctxs[p].plugin_bandwidth(xd)
+        assert _rel(r.h, ref.h) < 1e-6, (p, r.h, ref.h)
+        assert _rel(r.psi6, ref.psi6) < 1e-5 and _rel(r.psi4, ref.psi4) < 5e-6
+
+
+_ABS_CACHE = {}
+
+
+def _abs_block_sum(x, r, g, r0, r1, c0, c1):
+    key = (id(x), r, g, r0, r1, c0, c1)
+    if key not in _ABS_CACHE:
+        _ABS_CACHE[key] = _abs_block_sum_uncached(x, r, g, r0, r1, c0, c1)
+    return _ABS_CACHE[key]
+
+
+def _abs_block_sum_uncached(x, r, g, r0, r1, c0, c1):
+    from scipy import special
+    tot = 0.0
+    for i in range(r0, r1):
+        j0 = max(c0, i + 1)
+        if j0 >= c1:
+            continue
+        y = (x[i] - x[j0:c1]) / g
+        tot += np.sum(np.abs(special.eval_hermitenorm(r, y)) * np.exp(-0.5 * y * y)) / math.sqrt(2 * math.pi)
+    return tot
+
+
+def test_lognormal_1m_sampled_items_and_properties(kp, ctxs):
+    import torch
+    n = 1 << 20
+    z = synth.normal(n, 2)
+    x = 1e3 * np.exp(z) - 5e2           # the workload's sample
+    base = np.exp(z)                    # same sample before scale and shift
+    xd = torch.from_numpy(x).cuda()
+    r64 = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth(xd)
+    assert r64.status == 0 and r64.psi6 < 0 < r64.psi4
+    # sampled items of the Step IV stage at the FP64 path's g1, each against the oracle
+    for p, eps in ((kp.KDE_FP64_PLAIN, 1e-13), (kp.KDE_FP32_KAHAN, 2e-6)):
+        ctx = ctxs[p]
+        m = ctx.psi_num_items(n)
+        rng = np.random.default_rng(11)
+        for k in sorted({0, m // 7, m // 2, m - 1, *rng.integers(0, m, 3).tolist()}):
+            r0, r1, c0, c1 = ctx.psi_item_geometry(n, k)
+            got = ctx.psi_range(xd, 6, r64.g1, k, k + 1)
+            ref = oracle.block_sum(x, 6, r64.g1, r0, r1, c0, c1)
+            bound = eps * _abs_block_sum(x, 6, r64.g1, r0, r1, c0, c1) + 1e-300
+            assert abs(got - ref) <= bound, (p, k, got, ref, bound)
+    # scale and shift equivariance h(aX + b) = |a| h(X), and FP32 against FP64
+    hb = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth(torch.from_numpy(base).cuda()).h
+    assert _rel(r64.h, 1e3 * hb) < 1e-10
+    for p in (kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT):
+        r = ctxs[p].plugin_bandwidth(xd)
+        assert _rel(r.h, r64.h) < 1e-6, (p, r.h, r64.h)
+
+
+@pytest.fixture(scope="module")
+def batch512():
+    xs, names = synth.workload_batch(512, 3)
+    return xs, names
+
+
+def test_batch_512(kp, ctxs, batch512):
+    import torch
+    xs, _ = batch512
+    xds = [torch.from_numpy(x).cuda() for x in xs]
+    b64 = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth_batch(xds)
+    b32 = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth_batch(xds)
+    assert all(r.status == 0 for r in b64) and all(r.status == 0 for r in b32)
+    worst = max(_rel(a.h, b.h) for a, b in zip(b32, b64))
+    assert worst < 1e-6, worst
+    # oracle on every small sample and a few large ones
+    idx = [k for k, x in enumerate(xs) if x.size <= 4096]
+    idx += sorted(np.argsort([-x.size for x in xs])[:2].tolist())
+    for k in idx:
+        ref = oracle.plugin(xs[k])
+        assert _rel(b64[k].h, ref.h) < 1e-12, (k, xs[k].size)
+        assert _rel(b32[k].h, ref.h) < 1e-6, (k, xs[k].size)
+    # a batch result is bitwise the single-call result (decomposition depends on n only)
+    for k in (0, 1, 77, 311, 511):
+        s = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth(xds[k])
+        assert (s.h, s.psi6, s.psi4) == (b32[k].h, b32[k].psi6, b32[k].psi4)

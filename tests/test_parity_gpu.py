@@ -215,3 +215,23 @@ def test_f32_input_and_device_tensors(ctx64, ctx32):
     ref32 = oracle.plugin(x32.astype(np.float64))
     _check(ctx64.plugin_bandwidth(x32), ref32, TOL64, TOL64)
     _check(ctx64.plugin_bandwidth(torch.from_numpy(x32).cuda()), ref32, TOL64, TOL64)
+
+
+def test_autotune_tables_roundtrip(kp, tmp_path):
+    x = synth.bimodal(3000, 23)
+    ref = oracle.plugin(x)
+    p1 = str(tmp_path / "single.json")
+    t1 = kp.kde_autotune(kp.KDE_FP32_KAHAN, [1024, 4096], p1, mode=kp.KDE_TUNE_SINGLE, reps=2)
+    assert t1["rows_per_lane"] in (1, 2, 4) and len(t1["targets"]) == 2
+    with kp.Context(kp.KDE_FP32_KAHAN, tune_table=p1) as c:
+        cfg = c.config()
+        assert cfg["rows_per_lane"] == t1["rows_per_lane"] and cfg["blocks_per_cu"] == t1["blocks_per_cu"]
+        _check(c.plugin_bandwidth(x), ref, TOL32_H, TOL32_PSI)
+    p2 = str(tmp_path / "batch.json")
+    t2 = kp.kde_autotune(kp.KDE_FP32_KAHAN, [300, 1000, 2500], p2, mode=kp.KDE_TUNE_BATCH, reps=2)
+    assert t2["pair_budget"] > 0
+    with kp.Context(kp.KDE_FP32_KAHAN, tune_table=p2) as c:
+        res = c.plugin_bandwidth_batch([x, x[:500]])
+        _check(res[0], ref, TOL32_H, TOL32_PSI)
+    with pytest.raises(kp.KdeError):
+        kp.Context(kp.KDE_FP64_PLAIN, tune_table=p1)
