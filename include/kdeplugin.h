@@ -45,6 +45,12 @@
 
 #include <stdint.h>
 
+#if defined(__GNUC__)
+#define KDE_API __attribute__((visibility("default")))
+#else
+#define KDE_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -111,58 +117,58 @@ typedef struct {
 } kde_result;
 
 /* -------------------------------------------------------------- utilities */
-const char* kde_version(void);
-int kde_last_error(void);                  /* last status set on this thread */
-const char* kde_last_error_message(void);  /* human-readable detail for it   */
-const char* kde_strerror(int code);
+KDE_API const char* kde_version(void);
+KDE_API int kde_last_error(void);                  /* last status set on this thread */
+KDE_API const char* kde_last_error_message(void);  /* human-readable detail for it   */
+KDE_API const char* kde_strerror(int code);
 
 /* Fill *opt with the defaults listed above. */
-void kde_options_init(kde_options* opt);
+KDE_API void kde_options_init(kde_options* opt);
 
 /* Create a context on opt->device (opt may be NULL for defaults).  The
  * context owns its device workspace (work lists, per-item partial sums,
  * per-sample state), cached hipGraphs and the tile configuration. */
-int kde_ctx_create(kde_ctx** out, const kde_options* opt);
-void kde_ctx_destroy(kde_ctx* ctx);
+KDE_API int kde_ctx_create(kde_ctx** out, const kde_options* opt);
+KDE_API void kde_ctx_destroy(kde_ctx* ctx);
 
 /* Tile configuration actually in use: rows per lane, threads per block,
  * rows per tile, persistent blocks per CU. */
-int kde_ctx_config(const kde_ctx* ctx, int32_t* rows_per_lane, int32_t* block_threads,
+KDE_API int kde_ctx_config(const kde_ctx* ctx, int32_t* rows_per_lane, int32_t* block_threads,
                    int32_t* tile_rows, int32_t* blocks_per_cu);
 
 /* Device time in milliseconds of the last synchronous call's launch on this
  * context (init kernel + persistent kernel), measured with HIP events
  * recorded on the caller's stream around the launch; -1 if none yet. */
-double kde_ctx_last_device_ms(const kde_ctx* ctx);
+KDE_API double kde_ctx_last_device_ms(const kde_ctx* ctx);
 
 /* Device timeline of sample `sample` of the last synchronous call on this
  * context: ms[k] = milliseconds from the start of the sample's first work
  * item to the moment stage k published its result (k = 0: mean, 1: sigma
  * and g1 (Steps I-III), 2: Psi6 and g2 (Steps IV-V), 3: Psi4 and h (Steps
  * VI-VII)); -1 for a stage that did not run.  From the GPU's 100 MHz clock. */
-int kde_ctx_last_timeline(const kde_ctx* ctx, int64_t sample, double* ms);
+KDE_API int kde_ctx_last_timeline(const kde_ctx* ctx, int64_t sample, double* ms);
 
 /* ------------------------------------------------------- literal calls */
 
 /* Psi_r(g) of equations (6)-(7) (Steps IV/VI with a caller-chosen g) for
  * r in {4, 6}: host pointer x[0..n), n >= 1, g > 0.  Synchronous, FP64
  * plain, default context.  Returns NaN on error. */
-double kde_psi(const double* x, int64_t n, int r, double g);
+KDE_API double kde_psi(const double* x, int64_t n, int r, double g);
 
 /* h of Algorithm 1 (Steps I-VII) for host samples x[0..n), n >= 2.
  * Synchronous, FP64 plain, default context.  Returns NaN on error. */
-double kde_plugin_bandwidth(const double* x, int64_t n);
+KDE_API double kde_plugin_bandwidth(const double* x, int64_t n);
 
 /* --------------------------------------------------------- context calls */
 
 /* Psi_r(g) for samples x (mem_kind KDE_MEM_HOST/DEVICE, dtype KDE_F64/F32),
  * in the context's precision.  *out receives the value.  Synchronous. */
-int kde_psi_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r,
+KDE_API int kde_psi_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r,
                double g, kde_stream stream, double* out);
 
 /* Algorithm 1 for one sample; *out receives every intermediate.  The result's
  * status field repeats the return code.  Synchronous. */
-int kde_plugin_bandwidth_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype,
+KDE_API int kde_plugin_bandwidth_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype,
                             kde_stream stream, kde_result* out);
 
 /* Algorithm 1 for count independent samples xs[k][0..ns[k]) (all host or all
@@ -172,18 +178,18 @@ int kde_plugin_bandwidth_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind
  * succeeded, and per-sample failures are reported in out[k].status.  Each
  * out[k] is bitwise identical to what kde_plugin_bandwidth_ex returns for the
  * same sample on the same context.  Synchronous. */
-int kde_plugin_bandwidth_batch(kde_ctx* ctx, const void* const* xs, const int64_t* ns,
+KDE_API int kde_plugin_bandwidth_batch(kde_ctx* ctx, const void* const* xs, const int64_t* ns,
                                int64_t count, int mem_kind, kde_result* out, kde_stream stream);
 
 /* ---------------------------------------------- work decomposition / shards */
 
 /* Number of pair work items of one Psi stage for a sample of size n on this
  * context (the decomposition depends on n and the tile configuration only). */
-int64_t kde_psi_num_items(const kde_ctx* ctx, int64_t n);
+KDE_API int64_t kde_psi_num_items(const kde_ctx* ctx, int64_t n);
 
 /* Rectangle of the pair matrix covered by pair item `item`: rows [r0, r1),
  * columns [c0, c1), of which only the pairs with column > row are summed. */
-int kde_psi_item_geometry(const kde_ctx* ctx, int64_t n, int64_t item, int64_t* r0,
+KDE_API int kde_psi_item_geometry(const kde_ctx* ctx, int64_t n, int64_t item, int64_t* r0,
                           int64_t* r1, int64_t* c0, int64_t* c1);
 
 /* Partial sum of one Psi stage over the contiguous pair items
@@ -192,9 +198,71 @@ int kde_psi_item_geometry(const kde_ctx* ctx, int64_t n, int64_t item, int64_t* 
  * This is one shard of Step IV/VI: the shards of a partition of
  * [0, kde_psi_num_items) add up to the full strict-upper-triangle sum.
  * Synchronous. */
-int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r,
+KDE_API int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r,
                   double g, int64_t item_begin, int64_t item_end, kde_stream stream,
                   double* partial);
+
+/* ----------------------------------------------------------------- server */
+
+/* A continuous-batching server: requests (one sample each) may be submitted
+ * at any time; the server admits them (first come first served, or smallest
+ * n first) into at most max_active slots against a device-memory budget,
+ * keeps admitted samples resident on the device, and runs steps.  A step is
+ * one launch of the persistent kernel over the next work items of every
+ * active request, taken round-robin up to step_pairs pair evaluations
+ * (processor sharing), so a request that arrives while others run joins at
+ * the next step and its work overlaps theirs on the device.  Each result is
+ * bitwise what kde_plugin_bandwidth_ex returns for the same sample on the
+ * same context.  Steps are queued two deep on the server's own stream.
+ * A server uses its context exclusively; neither is thread-safe. */
+#define KDE_SERVE_FCFS 0
+#define KDE_SERVE_SJF 1
+
+typedef struct kde_server kde_server;
+
+typedef struct {
+    int64_t mem_budget;  /* device bytes of admitted requests: their samples (copied in, or
+                            left in caller device memory) and partial sums (default 8 GiB)    */
+    int64_t step_pairs;  /* pair evaluations per step across all requests (default 2^34)     */
+    int32_t max_active;  /* requests on the device at once (default 64)                       */
+    int32_t policy;      /* KDE_SERVE_FCFS (default) or KDE_SERVE_SJF admission order         */
+} kde_server_options;
+
+typedef struct {
+    int64_t id;          /* the id kde_server_submit returned                                 */
+    int64_t n;
+    kde_result result;   /* as kde_plugin_bandwidth_ex would return it                       */
+    double t_submit_ms;  /* host steady clock (ms) at submission, admission, and at the step  */
+    double t_admit_ms;   /* retirement that observed the result                               */
+    double t_done_ms;
+} kde_completion;
+
+typedef struct {
+    int32_t active, queued, inflight_steps, reserved;
+    int64_t steps, arena_used, completed_unread;  /* arena_used: bytes counted against the budget */
+    double pairs_done;   /* n(n-1) summed over completed requests                             */
+} kde_server_stats;
+
+KDE_API void kde_server_options_init(kde_server_options* opt);
+/* Allocates the arena (mem_budget bytes) on ctx's device. */
+KDE_API int kde_server_create(kde_server** out, kde_ctx* ctx, const kde_server_options* opt);
+/* Waits for the server's stream, then frees everything it owns. */
+KDE_API void kde_server_destroy(kde_server* srv);
+/* Queue one FP64 sample x[0..n) (host or device memory).  Host samples are
+ * copied to the device at admission, so x must stay valid until the request
+ * is admitted (device samples: until it completes).  *id identifies it.
+ * KDE_ENOMEM if it could never fit the memory budget. */
+KDE_API int kde_server_submit(kde_server* srv, const void* x, int64_t n, int mem_kind, int64_t* id);
+/* Remove a request that is still queued; KDE_EBUSY once admitted. */
+KDE_API int kde_server_cancel(kde_server* srv, int64_t id);
+/* Retire finished steps, admit queued requests, and launch the next step if
+ * fewer than two are queued.  block != 0 waits when the device is the
+ * bottleneck (two steps queued, or nothing new to launch).  stats may be NULL. */
+KDE_API int kde_server_step(kde_server* srv, int32_t block, kde_server_stats* stats);
+/* Move up to max finished requests into out[]; *got receives the count. */
+KDE_API int kde_server_poll(kde_server* srv, kde_completion* out, int32_t max, int32_t* got);
+/* Step until every submitted request has finished. */
+KDE_API int kde_server_drain(kde_server* srv);
 
 /* ------------------------------------------------------------- autotuner */
 
@@ -215,7 +283,7 @@ int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtyp
  * prints every timing to stderr.  Synchronous. */
 #define KDE_TUNE_SINGLE 0
 #define KDE_TUNE_BATCH 1
-int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t count, int32_t mode,
+KDE_API int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t count, int32_t mode,
                  int32_t reps, const char* out_path, int32_t verbose);
 
 #ifdef __cplusplus

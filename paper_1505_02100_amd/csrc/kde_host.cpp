@@ -19,20 +19,18 @@
 #include <string>
 #include <vector>
 
-#include "kde_internal.h"
-
-namespace kde {
-hipError_t launch_init(State* states, int32_t count, uint32_t* ticket, hipStream_t s);
-hipError_t launch_persistent(int prec, int R, int grid, hipStream_t s, const LaunchArgs& a);
-hipError_t persistent_occupancy(int prec, int R, int* blocks_per_cu);
-}  // namespace kde
+#include "kde_runtime.h"
 
 using namespace kde;
+
+namespace kde {
+namespace rt {
 
 // ----------------------------------------------------------------- errors
 namespace {
 thread_local int t_err = KDE_OK;
 thread_local std::string t_msg;
+}  // namespace
 
 int set_err(int code, const std::string& msg) {
     t_err = code;
@@ -47,40 +45,26 @@ int ok() {
 int hip_fail(hipError_t e, const char* what) {
     return set_err(KDE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
-#define HIPCHK(call)                                   \
-    do {                                               \
-        hipError_t _e = (call);                        \
-        if (_e != hipSuccess) return hip_fail(_e, #call); \
-    } while (0)
+int last_error_code() { return t_err; }
+const char* last_error_text() { return t_msg.c_str(); }
 
 const double kPi = 3.14159265358979323846;
-constexpr int kBlock = 256;           // threads per block of the persistent kernel
-constexpr int64_t kMomentChunk = 8192;  // elements per moment item (32 per thread)
-constexpr uint64_t kTimeoutTicks = 20ull * 100000000ull;  // 20 s at the 100 MHz wall clock
 
-// ------------------------------------------------------------ device buffer
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
+int DevBuf::ensure(size_t need, const char* what) {
+    if (need <= bytes) return KDE_OK;
+    if (p) {
+        (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
     }
-    int ensure(size_t need, const char* what) {
-        if (need <= bytes) return KDE_OK;
-        if (p) {
-            (void)hipFree(p);
-            p = nullptr;
-            bytes = 0;
-        }
-        hipError_t e = hipMalloc(&p, need);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return set_err(KDE_ENOMEM, std::string("hipMalloc ") + what + ": " + hipGetErrorString(e));
-        }
-        bytes = need;
-        return KDE_OK;
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(KDE_ENOMEM, std::string("hipMalloc ") + what + ": " + hipGetErrorString(e));
     }
-};
+    bytes = need;
+    return KDE_OK;
+}
 
 PolyConsts make_consts() {
     // exp(-y^2/2) = 2^(-k y^2) with k = log2(e)/2 (see kde_device.hip)
@@ -91,50 +75,14 @@ PolyConsts make_consts() {
     return pc;
 }
 
-}  // namespace
-
-// ------------------------------------------------------------------ plans
-struct Plan {
-    std::string key;
-    int32_t count = 0;                // samples
-    std::vector<Item> items;
-    std::vector<Desc> descs;          // host copy of what is on the device
-    bool descs_valid = false;
-    DevBuf d_items, d_descs, d_states, d_slots, d_ticket;
-    State* h_states = nullptr;        // pinned
-    int64_t n_slots = 0;
-    hipGraphExec_t exec = nullptr;
-    int grid = 0;
-    ~Plan() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (h_states) (void)hipHostFree(h_states);
-    }
-    size_t device_bytes() const {
-        return d_items.bytes + d_descs.bytes + d_states.bytes + d_slots.bytes + d_ticket.bytes;
-    }
-};
-
-struct kde_ctx {
-    std::vector<State> last_states;           // device state records of the last call
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket each launch on the caller's stream
-    double last_device_ms = -1.0;             // init + persistent kernel time of the last call
-    int device = 0;
-    int precision = KDE_FP64_PLAIN;
-    int64_t mem_budget = 0;
-    int R = 1;
-    int blocks_per_cu = 0;
-    int64_t target_items = 0;                 // 0 = by sample size
-    int64_t bucket_target[64] = {0};          // from a tune table: by floor(log2 n)
-    int64_t pair_budget = 0;                  // from a tune table: pairs per item for every n
-    int cus = 0;
-    PolyConsts pc{};
-    std::list<std::unique_ptr<Plan>> plans;   // most recently used first
-    size_t max_plans = 16;
-    DevBuf x_stage;                           // host samples copied here
-    std::vector<DevBuf> batch_stage;          // unused slots kept for reuse
-};
-
-namespace {
+DeviceGuard::DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+}
+DeviceGuard::~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+}
 
 // Pair work items per stage: small samples favour fewer, larger items (less
 // per-item latency), large ones more items (a shorter tail at the end of each
@@ -213,11 +161,6 @@ int load_tune_table(const char* path, TuneTable* tt) {
     return KDE_OK;
 }
 
-// Pair-item decomposition of the strict upper triangle for a sample of size n.
-struct PairGeom {
-    int64_t n, TI, W, RB;
-};
-
 PairGeom pair_geom(const kde_ctx* c, int64_t n) {
     PairGeom g{};
     g.n = n;
@@ -264,19 +207,66 @@ bool pair_item_at(const PairGeom& g, int64_t k, int64_t* rb, int64_t* cb) {
     return false;
 }
 
-struct SampleSpec {
-    const void* x;
-    int64_t n;
-    int32_t dtype;
-    int32_t mode;
-    int32_t psi_r;
-    double psi_g;
-    int64_t item_begin, item_end;  // pair-item range (MODE_PSI); [0, -1) = all
-};
-
 int64_t moment_chunk(int64_t n) {
     // at most 4096 moment items per sample
     return std::max<int64_t>(kMomentChunk, (n + 4095) / 4096);
+}
+
+int64_t describe_sample(const kde_ctx* c, const SampleSpec& ss, Desc* d) {
+    *d = Desc{};
+    d->x = ss.x;
+    d->n = ss.n;
+    d->dtype = ss.dtype;
+    d->mode = ss.mode;
+    d->psi_r = ss.psi_r;
+    d->psi_g = ss.psi_g;
+    d->chunk = (int32_t)moment_chunk(ss.n);
+    const PairGeom g = pair_geom(c, ss.n);
+    d->W = g.W;
+    const int64_t nm = (ss.n + d->chunk - 1) / d->chunk;
+    d->n_items[ST_SUM] = (int32_t)nm;
+    d->n_items[ST_SSQ] = (int32_t)nm;
+    const int64_t np = pair_item_count(g);
+    if (ss.mode == MODE_PLUGIN) {
+        d->n_items[ST_PSI6] = (int32_t)np;
+        d->n_items[ST_PSI4] = (int32_t)np;
+    } else {
+        const int64_t b = std::max<int64_t>(0, ss.item_begin);
+        const int64_t e = ss.item_end < 0 ? np : std::min(np, ss.item_end);
+        const int st = ss.psi_r == 6 ? ST_PSI6 : ST_PSI4;
+        d->n_items[st] = (int32_t)std::max<int64_t>(0, e - b);
+    }
+    int64_t slots = 0;
+    for (int s = 0; s < NUM_STAGES; ++s) slots += d->n_items[s];
+    return slots;
+}
+
+void sample_items(const kde_ctx* c, int32_t ds, const Desc& d, const SampleSpec& ss,
+                  std::vector<Item>* per_stage) {
+    for (int s = 0; s < NUM_STAGES; ++s) {
+        std::vector<Item>& out = per_stage[s];
+        const int32_t cnt = d.n_items[s];
+        if (cnt == 0) continue;
+        int32_t wait = -1;
+        if (s == ST_SSQ) wait = ST_SUM;
+        if (s == ST_PSI6) wait = ST_SSQ;
+        if (s == ST_PSI4) wait = d.mode == MODE_PLUGIN ? ST_PSI6 : ST_SSQ;
+        if (s == ST_SUM || s == ST_SSQ) {
+            for (int32_t q = 0; q < cnt; ++q) out.push_back(Item{ds, s, wait, q, 0, 0, d.slot_base[s] + q});
+        } else {
+            const PairGeom g = pair_geom(c, d.n);
+            const int64_t first = d.mode == MODE_PLUGIN ? 0 : std::max<int64_t>(0, ss.item_begin);
+            int64_t rb = 0, cb = 0;
+            pair_item_at(g, first, &rb, &cb);
+            for (int32_t q = 0; q < cnt; ++q) {
+                out.push_back(Item{ds, s, wait, (int32_t)rb, (int32_t)cb, 0, d.slot_base[s] + q});
+                if (++cb >= pair_items_in_row(g, rb)) {
+                    ++rb;
+                    cb = 0;
+                }
+            }
+        }
+    }
 }
 
 // Build the ordered work list: stage-major over samples (largest first), so
@@ -289,70 +279,20 @@ void build_items(const kde_ctx* c, Plan& p, const std::vector<SampleSpec>& ss) {
     for (int32_t k = 0; k < m; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return ss[a].n > ss[b].n; });
-    for (int32_t k = 0; k < m; ++k) {
-        Desc& d = p.descs[k];
-        d.x = ss[k].x;
-        d.n = ss[k].n;
-        d.dtype = ss[k].dtype;
-        d.mode = ss[k].mode;
-        d.psi_r = ss[k].psi_r;
-        d.psi_g = ss[k].psi_g;
-        d.chunk = (int32_t)moment_chunk(ss[k].n);
-        const PairGeom g = pair_geom(c, ss[k].n);
-        d.W = g.W;
-        const int64_t nm = (ss[k].n + d.chunk - 1) / d.chunk;
-        d.n_items[ST_SUM] = (int32_t)nm;
-        d.n_items[ST_SSQ] = (int32_t)nm;
-        if (ss[k].mode == MODE_PLUGIN) {
-            const int64_t np = pair_item_count(g);
-            d.n_items[ST_PSI6] = (int32_t)np;
-            d.n_items[ST_PSI4] = (int32_t)np;
-        } else {
-            const int64_t np = pair_item_count(g);
-            const int64_t b = std::max<int64_t>(0, ss[k].item_begin);
-            const int64_t e = ss[k].item_end < 0 ? np : std::min(np, ss[k].item_end);
-            const int st = ss[k].psi_r == 6 ? ST_PSI6 : ST_PSI4;
-            d.n_items[st] = (int32_t)std::max<int64_t>(0, e - b);
-        }
-    }
-    // slots: contiguous per (sample, stage)
     int64_t slot = 0;
-    for (int32_t k = 0; k < m; ++k)
-        for (int s = 0; s < NUM_STAGES; ++s) {
+    for (int32_t k = 0; k < m; ++k) {
+        describe_sample(c, ss[k], &p.descs[k]);
+        for (int s = 0; s < NUM_STAGES; ++s) {  // slots: contiguous per (sample, stage)
             p.descs[k].slot_base[s] = slot;
             slot += p.descs[k].n_items[s];
         }
+    }
     p.n_slots = slot;
+    std::vector<Item> per_stage[NUM_STAGES];
+    for (int32_t oi = 0; oi < m; ++oi) sample_items(c, order[oi], p.descs[order[oi]], ss[order[oi]], per_stage);
     p.items.clear();
     p.items.reserve((size_t)slot);
-    for (int s = 0; s < NUM_STAGES; ++s) {
-        for (int32_t oi = 0; oi < m; ++oi) {
-            const int32_t k = order[oi];
-            const Desc& d = p.descs[k];
-            const int32_t cnt = d.n_items[s];
-            if (cnt == 0) continue;
-            int32_t wait = -1;
-            if (s == ST_SSQ) wait = ST_SUM;
-            if (s == ST_PSI6) wait = ST_SSQ;
-            if (s == ST_PSI4) wait = d.mode == MODE_PLUGIN ? ST_PSI6 : ST_SSQ;
-            if (s == ST_SUM || s == ST_SSQ) {
-                for (int32_t q = 0; q < cnt; ++q)
-                    p.items.push_back(Item{k, s, wait, q, 0, 0, d.slot_base[s] + q});
-            } else {
-                const PairGeom g = pair_geom(c, d.n);
-                const int64_t first = d.mode == MODE_PLUGIN ? 0 : std::max<int64_t>(0, ss[k].item_begin);
-                int64_t rb = 0, cb = 0;
-                pair_item_at(g, first, &rb, &cb);
-                for (int32_t q = 0; q < cnt; ++q) {
-                    p.items.push_back(Item{k, s, wait, (int32_t)rb, (int32_t)cb, 0, d.slot_base[s] + q});
-                    if (++cb >= pair_items_in_row(g, rb)) {
-                        ++rb;
-                        cb = 0;
-                    }
-                }
-            }
-        }
-    }
+    for (int s = 0; s < NUM_STAGES; ++s) p.items.insert(p.items.end(), per_stage[s].begin(), per_stage[s].end());
 }
 
 int grid_for(const kde_ctx* c, int64_t n_items) {
@@ -523,18 +463,6 @@ int finish(kde_ctx* c, Plan& p, hipStream_t s) {
     return KDE_OK;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
 std::string key_single(const char* tag, int64_t n, int dtype, int extra1 = 0, int64_t e2 = 0,
                        int64_t e3 = 0) {
     char buf[160];
@@ -572,16 +500,19 @@ int psi_common(kde_ctx* c, const void* x, int64_t n, int mem_kind, int dtype, in
     return KDE_OK;
 }
 
-}  // namespace
+}  // namespace rt
+}  // namespace kde
+
+using namespace kde::rt;
 
 // ================================================================ C ABI
 extern "C" {
 
 const char* kde_version(void) { return "libkdeplugin 0.1 (gfx950)"; }
 
-int kde_last_error(void) { return t_err; }
+int kde_last_error(void) { return last_error_code(); }
 
-const char* kde_last_error_message(void) { return t_msg.c_str(); }
+const char* kde_last_error_message(void) { return last_error_text(); }
 
 const char* kde_strerror(int code) {
     switch (code) {

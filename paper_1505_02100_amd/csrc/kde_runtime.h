@@ -1,0 +1,139 @@
+// Host-side internals shared by the translation units of libkdeplugin's
+// runtime (contexts, plans, the work decomposition, the server).  Not part of
+// the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <list>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kde_internal.h"
+
+namespace kde {
+hipError_t launch_init(State* states, int32_t count, uint32_t* ticket, hipStream_t s);
+hipError_t launch_persistent(int prec, int R, int grid, hipStream_t s, const LaunchArgs& a);
+hipError_t persistent_occupancy(int prec, int R, int* blocks_per_cu);
+}  // namespace kde
+
+namespace kde {
+namespace rt {
+
+// Thread-local last error (kde_last_error / kde_last_error_message).
+int set_err(int code, const std::string& msg);
+int ok();
+int hip_fail(hipError_t e, const char* what);
+
+#define HIPCHK(call)                                           \
+    do {                                                       \
+        hipError_t _e = (call);                                \
+        if (_e != hipSuccess) return ::kde::rt::hip_fail(_e, #call); \
+    } while (0)
+
+constexpr int kBlock = 256;             // threads per block of the persistent kernel
+constexpr int64_t kMomentChunk = 8192;  // elements per moment item (32 per thread)
+constexpr uint64_t kTimeoutTicks = 20ull * 100000000ull;  // 20 s at the 100 MHz wall clock
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int ensure(size_t need, const char* what);
+};
+
+// Everything one launch of the persistent kernel needs for a fixed shape.
+struct Plan {
+    std::string key;
+    int32_t count = 0;                // samples
+    std::vector<Item> items;
+    std::vector<Desc> descs;          // host copy of what is on the device
+    bool descs_valid = false;
+    DevBuf d_items, d_descs, d_states, d_slots, d_ticket;
+    State* h_states = nullptr;        // pinned
+    int64_t n_slots = 0;
+    hipGraphExec_t exec = nullptr;
+    int grid = 0;
+    ~Plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (h_states) (void)hipHostFree(h_states);
+    }
+    size_t device_bytes() const {
+        return d_items.bytes + d_descs.bytes + d_states.bytes + d_slots.bytes + d_ticket.bytes;
+    }
+};
+
+// Pair-item decomposition of the strict upper triangle for a sample of size n.
+struct PairGeom {
+    int64_t n, TI, W, RB;
+};
+
+// One sample of a launch.
+struct SampleSpec {
+    const void* x;
+    int64_t n;
+    int32_t dtype;
+    int32_t mode;
+    int32_t psi_r;
+    double psi_g;
+    int64_t item_begin, item_end;  // pair-item range (MODE_PSI); [0, -1) = all
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+};
+
+PolyConsts make_consts();
+int64_t moment_chunk(int64_t n);
+int64_t pair_items_in_row(const PairGeom& g, int64_t rb);
+int64_t pair_chunk_width(const PairGeom& g, int64_t rb);
+int64_t pair_item_count(const PairGeom& g);
+bool pair_item_at(const PairGeom& g, int64_t k, int64_t* rb, int64_t* cb);
+void fill_result(const State& s, kde_result* r);
+int check_x(const void* x, int64_t n, int64_t nmin, int mem_kind, int dtype);
+
+}  // namespace rt
+}  // namespace kde
+
+struct kde_ctx {
+    std::vector<kde::State> last_states;      // device state records of the last call
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket each launch on the caller's stream
+    double last_device_ms = -1.0;             // init + persistent kernel time of the last call
+    int device = 0;
+    int precision = KDE_FP64_PLAIN;
+    int64_t mem_budget = 0;
+    int R = 1;
+    int blocks_per_cu = 0;
+    int64_t target_items = 0;                 // 0 = by sample size
+    int64_t bucket_target[64] = {0};          // from a tune table: by floor(log2 n)
+    int64_t pair_budget = 0;                  // from a tune table: pairs per item for every n
+    int cus = 0;
+    kde::PolyConsts pc{};
+    std::list<std::unique_ptr<kde::rt::Plan>> plans;  // most recently used first
+    size_t max_plans = 16;
+    kde::rt::DevBuf x_stage;                  // host samples copied here
+};
+
+namespace kde {
+namespace rt {
+PairGeom pair_geom(const kde_ctx* c, int64_t n);
+int grid_for(const kde_ctx* c, int64_t n_items);
+// Items of one sample, stage by stage, appended to `out` (slot numbers from
+// slot_base[] of `d`, which must already be filled).  Used by the server.
+void sample_items(const kde_ctx* c, int32_t ds, const Desc& d, const SampleSpec& ss,
+                  std::vector<Item>* per_stage);
+// Fill the descriptor of one sample (everything but slot_base) and return the
+// number of slots it needs.
+int64_t describe_sample(const kde_ctx* c, const SampleSpec& ss, Desc* d);
+}  // namespace rt
+}  // namespace kde

@@ -81,6 +81,28 @@ class kde_result(ctypes.Structure):
         return "kde_result(" + ", ".join(f"{k}={v!r}" for k, v in self.as_dict().items()) + ")"
 
 
+class kde_server_options(ctypes.Structure):
+    _fields_ = [("mem_budget", ctypes.c_int64), ("step_pairs", ctypes.c_int64),
+                ("max_active", ctypes.c_int32), ("policy", ctypes.c_int32)]
+
+
+class kde_completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("n", ctypes.c_int64), ("result", kde_result),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double)]
+
+
+class kde_server_stats(ctypes.Structure):
+    _fields_ = [("active", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("inflight_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("steps", ctypes.c_int64), ("arena_used", ctypes.c_int64),
+                ("completed_unread", ctypes.c_int64), ("pairs_done", ctypes.c_double)]
+
+
+KDE_SERVE_FCFS = 0
+KDE_SERVE_SJF = 1
+
+
 class KdeError(RuntimeError):
     def __init__(self, code: int, where: str):
         msg = _lib.kde_last_error_message().decode(errors="replace")
@@ -122,6 +144,14 @@ _sig("kde_plugin_bandwidth_batch", ctypes.c_int, _P, ctypes.POINTER(_P), _PI64, 
 _sig("kde_ctx_last_timeline", ctypes.c_int, _P, _I64, ctypes.POINTER(_D))
 _sig("kde_ctx_last_device_ms", _D, _P)
 _sig("kde_psi_num_items", _I64, _P, _I64)
+_sig("kde_server_options_init", None, ctypes.POINTER(kde_server_options))
+_sig("kde_server_create", ctypes.c_int, ctypes.POINTER(_P), _P, ctypes.POINTER(kde_server_options))
+_sig("kde_server_destroy", None, _P)
+_sig("kde_server_submit", ctypes.c_int, _P, _P, _I64, ctypes.c_int, _PI64)
+_sig("kde_server_cancel", ctypes.c_int, _P, _I64)
+_sig("kde_server_step", ctypes.c_int, _P, _I32, ctypes.POINTER(kde_server_stats))
+_sig("kde_server_poll", ctypes.c_int, _P, ctypes.POINTER(kde_completion), _I32, _PI32)
+_sig("kde_server_drain", ctypes.c_int, _P)
 _sig("kde_autotune", ctypes.c_int, ctypes.POINTER(kde_options), _PI64, _I32, _I32, _I32, ctypes.c_char_p,
      _I32)
 _sig("kde_psi_item_geometry", ctypes.c_int, _P, _I64, _I64, _PI64, _PI64, _PI64, _PI64)
@@ -313,6 +343,49 @@ def kde_psi_range(ctx: int, x, r: int, g: float, item_begin: int, item_end: int)
     _check(_lib.kde_psi_range(ctx, s.ptr, s.n, s.mem, s.dtype, int(r), float(g), int(item_begin),
                               int(item_end), s.stream, ctypes.byref(out)), "kde_psi_range")
     return out.value
+
+
+def kde_server_options_init() -> kde_server_options:
+    o = kde_server_options()
+    _lib.kde_server_options_init(ctypes.byref(o))
+    return o
+
+
+def kde_server_create(ctx: int, opts: kde_server_options) -> int:
+    h = _P()
+    _check(_lib.kde_server_create(ctypes.byref(h), ctx, ctypes.byref(opts)), "kde_server_create")
+    return h.value
+
+
+def kde_server_destroy(srv: int) -> None:
+    _lib.kde_server_destroy(srv)
+
+
+def kde_server_submit(srv: int, ptr: int, n: int, mem_kind: int) -> int:
+    rid = _I64()
+    _check(_lib.kde_server_submit(srv, ptr, int(n), int(mem_kind), ctypes.byref(rid)), "kde_server_submit")
+    return rid.value
+
+
+def kde_server_cancel(srv: int, rid: int) -> None:
+    _check(_lib.kde_server_cancel(srv, int(rid)), "kde_server_cancel")
+
+
+def kde_server_step(srv: int, block: bool = False) -> kde_server_stats:
+    st = kde_server_stats()
+    _check(_lib.kde_server_step(srv, int(bool(block)), ctypes.byref(st)), "kde_server_step")
+    return st
+
+
+def kde_server_poll(srv: int, max_items: int = 4096) -> List[kde_completion]:
+    buf = (kde_completion * max_items)()
+    got = _I32()
+    _check(_lib.kde_server_poll(srv, buf, max_items, ctypes.byref(got)), "kde_server_poll")
+    return [buf[k] for k in range(got.value)]
+
+
+def kde_server_drain(srv: int) -> None:
+    _check(_lib.kde_server_drain(srv), "kde_server_drain")
 
 
 KDE_TUNE_SINGLE = 0

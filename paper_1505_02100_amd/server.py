@@ -1,0 +1,179 @@
+"""Continuous-batching bandwidth-selection server (Python front end).
+
+The scheduling engine is native (kde_server_* in libkdeplugin): admission into
+slots against a device-memory budget, resident samples, and steps that each
+launch the persistent kernel over the next work items of every active request.
+This module keeps the Python-side bookkeeping: the arrival queue of a trace,
+the lifetime of device sample tensors, and latency statistics.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import kdeplugin as kp
+from . import synth
+
+
+@dataclass
+class Completion:
+    id: int
+    n: int
+    h: float
+    status: int
+    psi6: float
+    psi4: float
+    t_submit_ms: float
+    t_admit_ms: float
+    t_done_ms: float
+    arrival_s: Optional[float] = None
+    dist: Optional[str] = None
+    seed: Optional[int] = None
+
+    @property
+    def latency_ms(self) -> float:
+        return self.t_done_ms - self.t_submit_ms
+
+
+class Server:
+    """Owns a kde_server on a context; keeps submitted device tensors alive
+    until their request completes."""
+
+    def __init__(self, ctx: "kp.Context", mem_budget: int = 8 << 30, max_active: int = 64,
+                 step_pairs: int = 1 << 34, policy: str = "fcfs"):
+        o = kp.kde_server_options_init()
+        o.mem_budget = int(mem_budget)
+        o.max_active = int(max_active)
+        o.step_pairs = int(step_pairs)
+        o.policy = {"fcfs": kp.KDE_SERVE_FCFS, "sjf": kp.KDE_SERVE_SJF}[policy]
+        self.ctx = ctx
+        self.options = o
+        self.handle = kp.kde_server_create(ctx.handle, o)
+        self._keep: Dict[int, object] = {}
+
+    def close(self):
+        if self.handle:
+            kp.kde_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, x) -> int:
+        s = kp._Samples(x)
+        if s.dtype != kp.KDE_F64:
+            raise TypeError("server samples must be float64")
+        rid = kp.kde_server_submit(self.handle, s.ptr, s.n, s.mem)
+        self._keep[rid] = s.keep
+        return rid
+
+    def cancel(self, rid: int) -> None:
+        kp.kde_server_cancel(self.handle, rid)
+        self._keep.pop(rid, None)
+
+    def step(self, block: bool = False) -> kp.kde_server_stats:
+        return kp.kde_server_step(self.handle, block)
+
+    def poll(self) -> List[Completion]:
+        out = []
+        for c in kp.kde_server_poll(self.handle):
+            self._keep.pop(c.id, None)
+            r = c.result
+            out.append(Completion(c.id, c.n, r.h, r.status, r.psi6, r.psi4, c.t_submit_ms, c.t_admit_ms,
+                                  c.t_done_ms))
+        return out
+
+    def drain(self) -> List[Completion]:
+        kp.kde_server_drain(self.handle)
+        return self.poll()
+
+
+def percentile(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else math.nan
+
+
+def serve_trace(ctx: "kp.Context", trace, duration_s: float, mem_budget: int = 8 << 30,
+                max_active: int = 64, step_pairs: int = 1 << 34, policy: str = "fcfs",
+                lookahead: int = 8, drain: bool = False, device: str = "cuda",
+                keep_samples: bool = False, log=None) -> dict:
+    """Replay `trace` (list of (arrival_s, n, dist, seed), sorted by arrival) in
+    wall-clock time for `duration_s` seconds.  A request is drawn on the
+    device (synth.draw_torch) and submitted when it has arrived and the
+    server has room for it (at most `lookahead` submitted but not yet
+    admitted); later arrivals wait in a host FIFO, as they would at a front
+    end.  Latency is measured from the arrival time (the server's timestamps
+    and time.monotonic() share the host's monotonic clock).  With
+    keep_samples the device samples of completed requests are returned too.
+    Returns completions and the offered and served load."""
+    import torch
+    srv = Server(ctx, mem_budget=mem_budget, max_active=max_active, step_pairs=step_pairs, policy=policy)
+    pending = list(trace)
+    pending.reverse()                    # pop() from the end = earliest arrival
+    waiting: List = []                   # arrived, not yet submitted
+    meta: Dict[int, tuple] = {}
+    samples: Dict[int, object] = {}
+    done: List[Completion] = []
+    t0 = time.monotonic()
+    offered_pairs = 0.0
+    arrived = 0
+    last_log = 0.0
+    while True:
+        now = time.monotonic() - t0
+        while pending and pending[-1][0] <= min(now, duration_s):
+            a = pending.pop()
+            waiting.append(a)
+            offered_pairs += a[1] * (a[1] - 1)
+            arrived += 1
+        stats = srv.step(block=False)
+        # submit arrived requests while the server has room for them
+        if policy == "sjf":
+            waiting.sort(key=lambda a: a[1])
+        while waiting and stats.queued < lookahead and stats.active + stats.queued < max_active:
+            a = waiting.pop(0)
+            x = synth.draw_torch(a[2], a[1], a[3], device=device)
+            rid = srv.submit(x)
+            meta[rid] = a
+            if keep_samples:
+                samples[rid] = x
+            stats = srv.step(block=False)
+        for c in srv.poll():
+            c.arrival_s, _, c.dist, c.seed = meta.pop(c.id)
+            done.append(c)
+        if log is not None and now - last_log > 5.0:
+            last_log = now
+            log(f"t={now:6.1f}s arrived={arrived} done={len(done)} active={stats.active} "
+                f"waiting={len(waiting)} steps={stats.steps}")
+        if now >= duration_s and not drain:
+            break
+        if now >= duration_s and drain and not waiting and stats.active == 0 and stats.queued == 0:
+            break
+        if not waiting and stats.active == 0 and stats.queued == 0 and not pending:
+            break
+        if stats.inflight_steps >= 1 and not waiting:
+            srv.step(block=True)
+    window = time.monotonic() - t0
+    stats = srv.step(block=False)
+    srv.close()
+    lat = [c.t_done_ms - (t0 + c.arrival_s) * 1e3 for c in done]
+    served = sum(c.n * (c.n - 1) for c in done)
+    return {"completions": done, "window_s": window, "arrived": arrived,
+            "offered_pair_evals_per_s": offered_pairs / max(duration_s, 1e-9),
+            "served_pair_evals_per_s": served / window,
+            "selections_per_s": len(done) / window,
+            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat) if lat else math.nan},
+            "backlog": {"waiting": len(waiting), "active": stats.active, "not_arrived": len(pending)},
+            "samples": samples}

@@ -169,3 +169,77 @@ def serving_trace(rate: float = 200.0, duration: float = 60.0, master: int = 4,
         out.append((t, n, d, splitmix64_scalar(master ^ (k + 0x5151))))
         k += 1
     return out
+
+
+# ---------------------------------------------------------------------------
+# The same counter-based generator written with torch integer ops, so that
+# serving workloads can draw their samples directly in device memory.  The
+# uniforms are bit-identical to Stream's; the normals go through the device
+# libm's log / cos / sin and may differ from numpy's in the last bit, so any
+# check of a device-drawn sample copies those exact bytes back first.
+# ---------------------------------------------------------------------------
+
+def _i64(v: int) -> int:
+    """Two's-complement int64 value of an unsigned 64-bit constant."""
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def _srl(z, s: int):
+    """Logical right shift of an int64 tensor."""
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def _mix64_t(z):
+    z = (z ^ _srl(z, 30)) * _i64(0xBF58476D1CE4E5B9)
+    z = (z ^ _srl(z, 27)) * _i64(0x94D049BB133111EB)
+    return z ^ _srl(z, 31)
+
+
+class TorchStream:
+    """Stream's counter-based SplitMix64 sequence on a torch device."""
+
+    def __init__(self, seed: int, device):
+        self.seed = _i64(seed & _MASK)
+        self.counter = 0
+        self.device = device
+
+    def words(self, m: int):
+        import torch
+        k = torch.arange(self.counter + 1, self.counter + 1 + m, dtype=torch.int64, device=self.device)
+        self.counter += m
+        return _mix64_t(self.seed + k * _i64(0x9E3779B97F4A7C15))
+
+    def uniform(self, m: int):
+        import torch
+        return _srl(self.words(m), 11).to(torch.float64) * (1.0 / 9007199254740992.0)
+
+    def uniform_open(self, m: int):
+        return 1.0 - self.uniform(m)
+
+    def normal(self, m: int):
+        import torch
+        half = (m + 1) // 2
+        u1 = self.uniform_open(half)
+        u2 = self.uniform(half)
+        r = torch.sqrt(-2.0 * torch.log(u1))
+        z = torch.cat([r * torch.cos(2.0 * math.pi * u2), r * torch.sin(2.0 * math.pi * u2)])
+        return z[:m]
+
+
+def draw_torch(dist: str, n: int, seed: int, device="cuda"):
+    """draw() on a torch device (same streams and transforms)."""
+    import torch
+    s = TorchStream(seed, device)
+    if dist == "normal":
+        return s.normal(n)
+    if dist == "bimodal":
+        pick = s.uniform(n) < 0.5
+        z = s.normal(n)
+        return torch.where(pick, -1.0, 1.0).to(torch.float64) + (2.0 / 3.0) * z
+    if dist == "t3":
+        z = s.normal(n)
+        w = s.normal(3 * n).reshape(3, n)
+        return z / torch.sqrt((w * w).sum(dim=0) / 3.0)
+    if dist == "lognormal":
+        return torch.exp(s.normal(n))
+    raise ValueError(f"unknown distribution {dist!r}")
