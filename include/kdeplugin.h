@@ -99,6 +99,8 @@ typedef struct {
     int32_t blocks_per_cu;   /* 0 = from the tune table / occupancy; else 1..16            */
     int32_t target_items;    /* 0 = default; pair work items per stage for large n         */
     int32_t reserved;
+    int64_t pair_budget;     /* 0 = default; else pair items of about this many pairs for
+                                every n (overrides target_items and the tune table)         */
 } kde_options;
 
 /* The outputs of Algorithm 1 for one sample.  psi6/psi4 are the estimates of
@@ -241,6 +243,7 @@ typedef struct {
     int32_t active, queued, inflight_steps, reserved;
     int64_t steps, arena_used, completed_unread;  /* arena_used: bytes counted against the budget */
     double pairs_done;   /* n(n-1) summed over completed requests                             */
+    double pairs_issued; /* pair evaluations (i < j) of every item launched so far           */
 } kde_server_stats;
 
 KDE_API void kde_server_options_init(kde_server_options* opt);

@@ -89,11 +89,11 @@ DeviceGuard::~DeviceGuard() {
 // stage).  Measured on MI355X for the FP32 kernel with 256-row tiles; a
 // context option or tune table overrides it.
 int64_t target_items_for(const kde_ctx* c, int64_t n) {
-    if (c->target_items > 0) return c->target_items;
     if (c->pair_budget > 0) {
         const double P = 0.5 * (double)n * (double)(n - 1);
         return std::max<int64_t>(1, (int64_t)(P / (double)c->pair_budget));
     }
+    if (c->target_items > 0) return c->target_items;
     int lg = 0;
     while (lg < 62 && ((int64_t)2 << lg) <= n) ++lg;
     for (int b = lg; b >= 0; --b)
@@ -547,7 +547,7 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     if (o.rows_per_lane != 0 && o.rows_per_lane != 1 && o.rows_per_lane != 2 && o.rows_per_lane != 4)
         return set_err(KDE_EINVAL, "rows_per_lane must be 0, 1, 2 or 4");
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 16) return set_err(KDE_EINVAL, "blocks_per_cu out of range");
-    if (o.mem_budget < 0 || o.target_items < 0) return set_err(KDE_EINVAL, "negative option");
+    if (o.mem_budget < 0 || o.target_items < 0 || o.pair_budget < 0) return set_err(KDE_EINVAL, "negative option");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev == 0) return set_err(KDE_EDEVICE, "no HIP device available");
@@ -561,7 +561,7 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     }
     auto c = std::make_unique<kde_ctx>();
     for (int b = 0; b < 64; ++b) c->bucket_target[b] = tt.bucket[b];
-    c->pair_budget = tt.pair_budget;
+    c->pair_budget = o.pair_budget > 0 ? o.pair_budget : tt.pair_budget;
     c->device = o.device;
     c->precision = o.precision;
     c->mem_budget = o.mem_budget;

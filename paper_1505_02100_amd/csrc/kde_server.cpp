@@ -88,9 +88,10 @@ struct Request {
     int32_t slot = -1;
     size_t off = 0, bytes = 0;        // arena block: [slots | sample copy]
     Desc desc{};
-    std::vector<Item> items[NUM_STAGES];
-    int stage = 0;                    // issue cursor
-    size_t next = 0;
+    PairGeom geom{};
+    int stage = 0;                    // issue cursor: stage, ordinal within it,
+    int64_t next = 0;                 // and (row block, chunk) for pair stages
+    int64_t rb = 0, cb = 0;
     double pairs = 0;                 // pair evaluations of the whole selection
     hipEvent_t copied = nullptr;      // sample copy done (host samples)
     bool wait_copy = false;
@@ -127,6 +128,7 @@ struct kde_server {
     double pairs_done = 0;
     int64_t steps = 0;
     size_t device_sample_bytes = 0;   // admitted samples that live in caller memory
+    double pairs_issued = 0;          // pair evaluations of all launched items
 };
 
 namespace {
@@ -177,10 +179,9 @@ int admit_one(kde_server* s, std::unique_ptr<Request>& rp) {
     } else {
         r.desc.x = r.x_user;
     }
-    // item lists with this request's slot index and slot numbers
-    SampleSpec sp{r.desc.x, r.n, KDE_F64, MODE_PLUGIN, 0, 0.0, 0, -1};
-    for (auto& v : r.items) v.clear();
-    sample_items(s->ctx, r.slot, r.desc, sp, r.items);
+    r.geom = pair_geom(s->ctx, r.n);
+    r.stage = 0;
+    r.next = r.rb = r.cb = 0;
     s->h_descs[r.slot] = r.desc;
     HIPCHK(hipMemcpyAsync((Desc*)s->d_descs.p + r.slot, s->h_descs + r.slot, sizeof(Desc), hipMemcpyHostToDevice,
                           s->stream));
@@ -206,14 +207,41 @@ int admit(kde_server* s) {
     return KDE_OK;
 }
 
-double item_pairs(const kde_ctx* c, const Request& r, const Item& it) {
+// Pair evaluations of a pair item: rows [r0, r1) x columns [c0, c1) with
+// column > row (diagonal items are partly empty).
+double item_pairs(const Request& r, const Item& it) {
     if (it.stage == ST_SUM || it.stage == ST_SSQ) return 0.0;
-    const PairGeom g = pair_geom(c, r.n);
-    const int64_t r0 = (int64_t)it.a * g.TI;
+    const PairGeom& g = r.geom;
+    const int64_t r0 = (int64_t)it.a * g.TI, r1 = std::min(r0 + g.TI, r.n);
     const int64_t w = pair_chunk_width(g, it.a);
     const int64_t c0 = r0 + (int64_t)it.b * w, c1 = std::min(c0 + w, r.n);
-    const int64_t rows = std::min(g.TI, r.n - r0);
-    return (double)rows * (double)(c1 - c0);  // upper bound (diagonal items are about half)
+    if (c0 >= r1) return (double)(r1 - r0) * (double)(c1 - c0);
+    double p = 0.0;
+    for (int64_t i = r0; i < r1; ++i) p += (double)std::max<int64_t>(0, c1 - std::max(c0, i + 1));
+    return p;
+}
+
+// The next unlisted item of a request (its cursor must not be past the end).
+Item next_item(Request& r) {
+    const Desc& d = r.desc;
+    const int s = r.stage;
+    int32_t wait = -1;
+    if (s == ST_SSQ) wait = ST_SUM;
+    if (s == ST_PSI6) wait = ST_SSQ;
+    if (s == ST_PSI4) wait = ST_PSI6;
+    Item it{r.slot, s, wait, 0, 0, 0, d.slot_base[s] + r.next};
+    if (s == ST_SUM || s == ST_SSQ) {
+        it.a = (int32_t)r.next;
+    } else {
+        it.a = (int32_t)r.rb;
+        it.b = (int32_t)r.cb;
+        if (++r.cb >= pair_items_in_row(r.geom, r.rb)) {
+            ++r.rb;
+            r.cb = 0;
+        }
+    }
+    ++r.next;
+    return it;
 }
 
 int launch_step(kde_server* s) {
@@ -232,9 +260,10 @@ int launch_step(kde_server* s) {
     // A request's cursor always points at its next unlisted item; when the last
     // one is listed, last_step records the step being built.
     auto advance = [](Request& r) {
-        while (r.stage < NUM_STAGES && r.next >= r.items[r.stage].size()) {
+        while (r.stage < NUM_STAGES && r.next >= r.desc.n_items[r.stage]) {
             ++r.stage;
             r.next = 0;
+            r.rb = r.cb = 0;
         }
     };
     size_t turn = s->rr % std::max<size_t>(1, m);
@@ -246,10 +275,11 @@ int launch_step(kde_server* s) {
             for (;;) {
                 advance(r);
                 if (r.stage >= NUM_STAGES) break;
-                const Item& it = r.items[r.stage][r.next++];
-                stage_lists[r.stage].push_back(it);
-                const double p = item_pairs(s->ctx, r, it);
+                const Item it = next_item(r);
+                stage_lists[it.stage].push_back(it);
+                const double p = item_pairs(r, it);
                 budget -= p;
+                s->pairs_issued += p;
                 if (p > 0) break;  // one pair item per turn
             }
             advance(r);
@@ -487,6 +517,7 @@ int kde_server_step(kde_server* s, int32_t block, kde_server_stats* stats) {
         stats->steps = s->steps;
         stats->arena_used = (int64_t)(s->arena->used() + s->device_sample_bytes);
         stats->pairs_done = s->pairs_done;
+        stats->pairs_issued = s->pairs_issued;
         stats->completed_unread = (int64_t)s->done.size();
     }
     return ok();

@@ -65,7 +65,8 @@ class kde_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mem_budget", ctypes.c_int64), ("tune_table", ctypes.c_char_p),
                 ("rows_per_lane", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("target_items", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("target_items", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pair_budget", ctypes.c_int64)]
 
 
 class kde_result(ctypes.Structure):
@@ -96,7 +97,8 @@ class kde_server_stats(ctypes.Structure):
     _fields_ = [("active", ctypes.c_int32), ("queued", ctypes.c_int32),
                 ("inflight_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("steps", ctypes.c_int64), ("arena_used", ctypes.c_int64),
-                ("completed_unread", ctypes.c_int64), ("pairs_done", ctypes.c_double)]
+                ("completed_unread", ctypes.c_int64), ("pairs_done", ctypes.c_double),
+                ("pairs_issued", ctypes.c_double)]
 
 
 KDE_SERVE_FCFS = 0
@@ -251,7 +253,7 @@ def kde_options_init() -> kde_options:
 
 def kde_ctx_create(precision: int = KDE_FP64_PLAIN, device: int = 0, mem_budget: int = 0,
                    rows_per_lane: int = 0, blocks_per_cu: int = 0, target_items: int = 0,
-                   tune_table: Optional[str] = None) -> int:
+                   tune_table: Optional[str] = None, pair_budget: int = 0) -> int:
     o = kde_options_init()
     o.device = device
     o.precision = precision
@@ -259,6 +261,7 @@ def kde_ctx_create(precision: int = KDE_FP64_PLAIN, device: int = 0, mem_budget:
     o.rows_per_lane = rows_per_lane
     o.blocks_per_cu = blocks_per_cu
     o.target_items = target_items
+    o.pair_budget = pair_budget
     o.tune_table = tune_table.encode() if tune_table else None
     h = _P()
     _check(_lib.kde_ctx_create(ctypes.byref(h), ctypes.byref(o)), "kde_ctx_create")

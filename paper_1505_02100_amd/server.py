@@ -167,12 +167,14 @@ def serve_trace(ctx: "kp.Context", trace, duration_s: float, mem_budget: int = 8
             srv.step(block=True)
     window = time.monotonic() - t0
     stats = srv.step(block=False)
+    issued = stats.pairs_issued
     srv.close()
     lat = [c.t_done_ms - (t0 + c.arrival_s) * 1e3 for c in done]
     served = sum(c.n * (c.n - 1) for c in done)
     return {"completions": done, "window_s": window, "arrived": arrived,
             "offered_pair_evals_per_s": offered_pairs / max(duration_s, 1e-9),
-            "served_pair_evals_per_s": served / window,
+            "completed_pair_evals_per_s": served / window,
+            "device_pair_evals_per_s": issued / window,
             "selections_per_s": len(done) / window,
             "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat) if lat else math.nan},
             "backlog": {"waiting": len(waiting), "active": stats.active, "not_arrived": len(pending)},
