@@ -307,6 +307,28 @@ __device__ __forceinline__ double centre_offset(int32_t rb) {
     return 0.5 * (f - floor(f)) - 0.25;
 }
 
+// Column tiles are software-pipelined: the values of the next tile are
+// loaded into registers (TJ / BLOCK per thread, all in flight together)
+// while the current tile is evaluated, then converted and stored to LDS.
+template <int BLOCK>
+__device__ __forceinline__ void load_cols(const View& d, int64_t cj, int64_t c1, double (&v)[TJ / BLOCK]) {
+#pragma unroll
+    for (int q = 0; q < TJ / BLOCK; ++q) {
+        const int64_t j = cj + threadIdx.x + (int64_t)q * BLOCK;
+        v[q] = j < c1 ? load_x(d.x, d.dtype, j) : 0.0;
+    }
+}
+
+template <typename T, int BLOCK>
+__device__ __forceinline__ void store_cols(T* tile, const double (&v)[TJ / BLOCK], int len, double mean,
+                                           double scale, double tau) {
+#pragma unroll
+    for (int q = 0; q < TJ / BLOCK; ++q) {
+        const int e = threadIdx.x + q * BLOCK;
+        if (e < len) tile[e] = (T)((v[q] - mean) * scale - tau);
+    }
+}
+
 template <int RO, bool SAFE, bool EXACT_K, int R, int BLOCK>
 __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double mean, double scale,
                                 const PolyConsts& pc, float* tile, double* red) {
@@ -334,12 +356,14 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
 
     int64_t c0, c1;
     item_columns(n, r0, d.W, cb, &c0, &c1);
+    double nv[TJ / BLOCK];
+    load_cols<BLOCK>(d, c0, c1, nv);
     for (int64_t cj = c0; cj < c1; cj += TJ) {
         const int len = (int)min((int64_t)TJ, c1 - cj);
         __syncthreads();
-        for (int e = tid; e < len; e += BLOCK)
-            tile[e] = (float)((load_x(d.x, d.dtype, cj + e) - mean) * scale - tau);
+        store_cols<float, BLOCK>(tile, nv, len, mean, scale, tau);
         __syncthreads();
+        if (cj + TJ < c1) load_cols<BLOCK>(d, cj + TJ, c1, nv);
 
         // columns inside this wave's row span: only j > i counts
         const int64_t ma = max(cj, wlo + 1), mb = min(cj + (int64_t)len, whi);
@@ -409,11 +433,14 @@ __device__ double pair_item_f64(const View& d, int32_t rb, int32_t cb, double me
     }
     int64_t c0, c1;
     item_columns(n, r0, d.W, cb, &c0, &c1);
+    double nv[TJ / BLOCK];
+    load_cols<BLOCK>(d, c0, c1, nv);
     for (int64_t cj = c0; cj < c1; cj += TJ) {
         const int len = (int)min((int64_t)TJ, c1 - cj);
         __syncthreads();
-        for (int e = tid; e < len; e += BLOCK) tile[e] = (load_x(d.x, d.dtype, cj + e) - mean) * scale;
+        store_cols<double, BLOCK>(tile, nv, len, mean, scale, 0.0);
         __syncthreads();
+        if (cj + TJ < c1) load_cols<BLOCK>(d, cj + TJ, c1, nv);
         const int64_t ma = max(cj, wlo + 1), mb = min(cj + (int64_t)len, whi);
         for (int64_t j = ma; j < mb; ++j) {
             const double uj = tile[j - cj];
@@ -534,20 +561,80 @@ __global__ void k_init(State* states, int32_t count, uint32_t* ticket) {
     if (i == 0) *ticket = 0u;
 }
 
+// Completion of `cnt` items of one (sample, stage) whose slots this block
+// has written: one release read-modify-write on the stage's counter.  The
+// block that brings the counter to the stage's item count sums the stage's
+// slots in index order (Neumaier) and runs the stage's scalar formulas.
+template <int PREC, int BLOCK>
+__device__ void complete_items(const LaunchArgs& A, const View& d, State* st, int32_t stage, uint32_t cnt,
+                               double* red, int32_t* sh_last) {
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        const uint32_t old = __hip_atomic_fetch_add(&st->done[stage], cnt, __ATOMIC_RELEASE,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        *sh_last = (old + cnt == (uint32_t)d.cnt) ? 1 : 0;
+    }
+    __syncthreads();
+    if (*sh_last) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int64_t base = d.base;
+        const int32_t n_slots = d.cnt;
+        // each thread sums its slots k = tid + BLOCK q in q order (Neumaier),
+        // loading U of them at a time so the loads overlap
+        constexpr int U = 8;
+        double s = 0.0, c = 0.0, m = 0.0;
+        for (int32_t k0 = tid; k0 < n_slots; k0 += BLOCK * U) {
+            Slot buf[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t k = k0 + u * BLOCK;
+                buf[u] = k < n_slots ? A.slots[base + k] : Slot{0.0, 0.0};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double tt = s + buf[u].v;
+                c += fabs(s) >= fabs(buf[u].v) ? (s - tt) + buf[u].v : (buf[u].v - tt) + s;
+                s = tt;
+                m = fmax(m, buf[u].aux);
+            }
+        }
+        const double tot = block_sum<BLOCK>(s + c, red);
+        const double mx = block_max<BLOCK>(m, red);
+        if (tid == 0) {
+            finalize_stage<PREC>(d, st, stage, tot, mx, A.pc);
+            __hip_atomic_store(&st->t_fin[stage], (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            st_release(&st->ready[stage], 1u);
+        }
+    }
+    __syncthreads();
+}
+
 // Memory-model cost on a multi-XCD device: an agent-scope release writes
 // back the XCD's L2 and an agent-scope acquire invalidates it, for every CU of
 // that XCD.  The loop therefore (i) fetches the next ticket with a relaxed
 // atomic one item ahead, (ii) waits with relaxed polling and issues one
 // acquire per (block, sample, stage) it has not seen published yet, caching
-// the published scalars in LDS, and (iii) completes an item with a single
-// release read-modify-write; only a stage's finaliser acquires the slots.
+// the published scalars in LDS, and (iii) counts its finished items of one
+// run of (sample, stage) items with a single release read-modify-write, as
+// soon as its prefetched next ticket lies past the run (or there is none);
+// only a stage's finaliser acquires the slots.
+//
+// Progress.  A block holds uncounted items of one (sample, stage) only, and
+// it counts them before it starts an item of another (sample, stage) (the
+// run rule does so at the end of the run; the check at the top of the loop
+// covers work lists whose runs are marked shorter).  So a block that waits
+// for a stage flag holds no uncounted items, a block that does not wait
+// finishes its item and takes the next ticket, and a block without tickets
+// has counted everything: every stage counter reaches its item count and
+// every flag is published.
 template <int PREC, int R, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
     using TileT = typename std::conditional<PREC >= 1, float, double>::type;
     __shared__ __align__(16) TileT tile[TJ];
     __shared__ double red[BLOCK / WAVE];
     __shared__ uint32_t sh_ticket;
-    __shared__ int32_t sh_status, sh_safe, sh_last;
+    __shared__ int32_t sh_status, sh_safe, sh_last, sh_flush;
     __shared__ int32_t sh_cds, sh_cwait;  // (sample, stage) whose published scalars are cached
     __shared__ double sh_mean, sh_scale;
 
@@ -558,6 +645,9 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         sh_cds = -1;
         sh_cwait = -1;
     }
+    // finished items not yet counted (same values in every thread)
+    int32_t pend_ds = -1, pend_stage = 0;
+    uint32_t pend_cnt = 0;
     for (;;) {
         if (tid == 0) {
             sh_ticket = next;
@@ -565,9 +655,16 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         }
         __syncthreads();
         const uint32_t t = sh_ticket;
-        if (t >= A.n_items) break;
+        const bool have = t < A.n_items;
+        Item it = {};
+        if (have) it = A.items[t];
+        if (pend_cnt != 0u && (!have || it.ds != pend_ds || it.stage != pend_stage)) {
+            complete_items<PREC, BLOCK>(A, load_view(A.descs + pend_ds, pend_stage), A.states + pend_ds,
+                                        pend_stage, pend_cnt, red, &sh_last);
+            pend_cnt = 0u;
+        }
+        if (!have) break;
 
-        const Item it = A.items[t];
         const View d = load_view(A.descs + it.ds, it.stage);
         State* st = A.states + it.ds;
 
@@ -641,44 +738,16 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
             s.v = v;
             s.aux = aux;
             A.slots[it.slot] = s;
-            const uint32_t old = __hip_atomic_fetch_add(&st->done[it.stage], 1u, __ATOMIC_RELEASE,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-            sh_last = (old + 1u == (uint32_t)d.cnt) ? 1 : 0;
+            sh_flush = next >= (uint32_t)it.run_end ? 1 : 0;
         }
+        pend_ds = it.ds;
+        pend_stage = it.stage;
+        ++pend_cnt;
         __syncthreads();
-        if (sh_last) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const int64_t base = d.base;
-            const int32_t cnt = d.cnt;
-            // each thread sums its slots k = tid + BLOCK q in q order (Neumaier),
-            // loading U of them at a time so the loads overlap
-            constexpr int U = 8;
-            double s = 0.0, c = 0.0, m = 0.0;
-            for (int32_t k0 = tid; k0 < cnt; k0 += BLOCK * U) {
-                Slot buf[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int32_t k = k0 + u * BLOCK;
-                    buf[u] = k < cnt ? A.slots[base + k] : Slot{0.0, 0.0};
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const double tt = s + buf[u].v;
-                    c += fabs(s) >= fabs(buf[u].v) ? (s - tt) + buf[u].v : (buf[u].v - tt) + s;
-                    s = tt;
-                    m = fmax(m, buf[u].aux);
-                }
-            }
-            const double tot = block_sum<BLOCK>(s + c, red);
-            const double mx = block_max<BLOCK>(m, red);
-            if (tid == 0) {
-                finalize_stage<PREC>(d, st, it.stage, tot, mx, A.pc);
-                __hip_atomic_store(&st->t_fin[it.stage], (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                st_release(&st->ready[it.stage], 1u);
-            }
+        if (sh_flush) {
+            complete_items<PREC, BLOCK>(A, d, st, it.stage, pend_cnt, red, &sh_last);
+            pend_cnt = 0u;
         }
-        __syncthreads();
     }
 }
 

@@ -98,7 +98,11 @@ int64_t target_items_for(const kde_ctx* c, int64_t n) {
     while (lg < 62 && ((int64_t)2 << lg) <= n) ++lg;
     for (int b = lg; b >= 0; --b)
         if (c->bucket_target[b] > 0) return c->bucket_target[b];
-    return n < (int64_t)1 << 17 ? 8192 : 32768;
+    // about 2^18 pairs per item (W = 1024 columns of a 256-row tile), at
+    // least 1024 items so small samples still spread over the device, at
+    // most 32768 so the work list and slots stay small
+    const double P = 0.5 * (double)n * (double)(n - 1);
+    return std::min<int64_t>(32768, std::max<int64_t>(1024, (int64_t)std::ceil(P / 262144.0)));
 }
 
 // Tune table (written by kde_autotune): a small JSON object
@@ -293,12 +297,25 @@ void build_items(const kde_ctx* c, Plan& p, const std::vector<SampleSpec>& ss) {
     p.items.clear();
     p.items.reserve((size_t)slot);
     for (int s = 0; s < NUM_STAGES; ++s) p.items.insert(p.items.end(), per_stage[s].begin(), per_stage[s].end());
+    // runs of consecutive items of one (sample, stage): a block counts its
+    // finished items of a run once its next ticket lies past the run
+    const int64_t total = (int64_t)p.items.size();
+    for (int64_t e = total; e > 0;) {
+        int64_t b = e - 1;
+        while (b > 0 && p.items[b - 1].ds == p.items[e - 1].ds && p.items[b - 1].stage == p.items[e - 1].stage) --b;
+        for (int64_t q = b; q < e; ++q) p.items[q].run_end = (int32_t)e;
+        e = b;
+    }
 }
 
-int grid_for(const kde_ctx* c, int64_t n_items) {
-    int g = c->cus * std::max(1, c->blocks_per_cu);
-    if (n_items < g) g = (int)std::max<int64_t>(1, n_items);
-    return g;
+// Persistent blocks for a launch whose widest stage has `work` items: the
+// context's blocks per CU on every CU, but no more than half that many items
+// (blocks of a small launch then take two items per stage, and the CUs keep
+// some of their VALU share for the others) and never more than there are items.
+int grid_for(const kde_ctx* c, int64_t work) {
+    const int64_t full = (int64_t)c->cus * std::max(1, c->blocks_per_cu);
+    const int64_t w = std::max<int64_t>(1, work);
+    return (int)std::min(full, std::max(std::min<int64_t>(c->cus, w), w / 2));
 }
 
 int total_plan_bytes(const kde_ctx* c, size_t extra, size_t* out) {
@@ -332,7 +349,9 @@ int upload_plan(kde_ctx* c, Plan& p) {
     HIPCHK(hipHostMalloc((void**)&p.h_states, sizeof(State) * std::max(1, p.count), hipHostMallocDefault));
     if (!p.items.empty())
         HIPCHK(hipMemcpy(p.d_items.p, p.items.data(), sizeof(Item) * p.items.size(), hipMemcpyHostToDevice));
-    p.grid = grid_for(c, (int64_t)p.items.size());
+    int64_t per_stage[NUM_STAGES] = {0};
+    for (const Item& it : p.items) ++per_stage[it.stage];
+    p.grid = grid_for(c, *std::max_element(per_stage, per_stage + NUM_STAGES));
     return KDE_OK;
 }
 

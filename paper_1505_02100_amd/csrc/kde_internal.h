@@ -31,7 +31,10 @@ struct Item {
     int32_t wait;   // stage whose finaliser must have published first, or -1
     int32_t a;
     int32_t b;
-    int32_t pad;
+    // One past the ticket of the last item of the run of consecutive items
+    // of the same (sample, stage) this item belongs to in its work list;
+    // 0 makes the block count this item as soon as it is finished.
+    int32_t run_end;
     int64_t slot;   // index of this item's partial-sum slot
 };
 static_assert(sizeof(Item) == 32, "Item layout");

@@ -127,7 +127,7 @@ struct kde_ctx {
 namespace kde {
 namespace rt {
 PairGeom pair_geom(const kde_ctx* c, int64_t n);
-int grid_for(const kde_ctx* c, int64_t n_items);
+int grid_for(const kde_ctx* c, int64_t work);
 // Items of one sample, stage by stage, appended to `out` (slot numbers from
 // slot_base[] of `d`, which must already be filled).  Used by the server.
 void sample_items(const kde_ctx* c, int32_t ds, const Desc& d, const SampleSpec& ss,

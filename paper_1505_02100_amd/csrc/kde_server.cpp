@@ -244,6 +244,12 @@ Item next_item(Request& r) {
     return it;
 }
 
+// A step's items come from many requests, one pair item per request per
+// turn: one block per item up to the context's full grid.
+int step_grid(const kde_ctx* c, int64_t items) {
+    return (int)std::min<int64_t>((int64_t)c->cus * std::max(1, c->blocks_per_cu), std::max<int64_t>(1, items));
+}
+
 int launch_step(kde_server* s) {
     if (s->active.empty()) return KDE_OK;
     std::vector<Item> stage_lists[NUM_STAGES];
@@ -333,7 +339,7 @@ int launch_step(kde_server* s) {
     a.ticket = ticket;
     a.pc = s->ctx->pc;
     a.timeout_ticks = kTimeoutTicks;
-    HIPCHK(launch_persistent(s->ctx->precision, s->ctx->R, grid_for(s->ctx, (int64_t)total), s->stream, a));
+    HIPCHK(launch_persistent(s->ctx->precision, s->ctx->R, step_grid(s->ctx, (int64_t)total), s->stream, a));
     HIPCHK(hipMemcpyAsync(s->h_states[b], s->d_states.p, sizeof(State) * (size_t)s->opt.max_active,
                           hipMemcpyDeviceToHost, s->stream));
     Step st;
