@@ -39,7 +39,8 @@
 // y^2 into an additive shift (why the polynomial is not depressed), and a
 // small bias of v_exp_f32 (mean relative error about -3e-9).  So each row
 // keeps four FP32 accumulators (one per column of an LDS b128 read) that take
-// at most kFold terms each before they are added into the lane's FP64 sum.
+// at most kFold terms each; the four are then added pairwise in FP32 (a
+// 16-term pairwise sum) and the result goes into the lane's FP64 sum.
 // The one systematic error left by construction is the FP32 rounding of k
 // (relative 1.3e-8, i.e. the Gaussian taken at a bandwidth 7e-9 larger than
 // the polynomial's); the EXACT_K variant removes it with a two-term k,
@@ -54,10 +55,15 @@
 // FP64 pair arithmetic is the plain printed form: t = y^2,
 // p = ((t - 15) t + 45) t - 15 (resp. (t - 6) t + 3), exp(-t/2), FP64 sums.
 //
-// Cross-block reduction is deterministic: every item writes its own slot;
-// the block that completes the last item of a stage (atomic counter) sums
-// that stage's slots in index order and runs the stage's scalar formulas
-// (Steps I-III, V, VII) in FP64, then publishes them with a release flag.
+// Cross-block reduction is deterministic.  A moment item writes its own
+// slot, and the block that completes a moment stage's last item (atomic
+// counter) sums the stage's slots in index order.  A pair item's FP64
+// partial is added exactly, as a 128-bit fixed-point integer, into the
+// block's accumulator, which goes into the stage's accumulator with
+// integer atomics; integer addition does not depend on order, so the sum
+// is the same for every schedule and the finaliser reads it in one step.
+// The finaliser runs the stage's scalar formulas (Steps I-III, V, VII) in
+// FP64 and publishes them with a release flag.
 // Items of a later stage wait (acquire, bounded by a wall-clock limit) for
 // that flag.  Items of earlier stages always hold smaller tickets, and no
 // item waits on a later ticket, so the wait always ends.
@@ -282,21 +288,17 @@ template <int R>
 __device__ __forceinline__ void fold_f64(float (&acc)[R][4], double (&tot)[R]) {
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        tot[k] += ((double)acc[k][0] + (double)acc[k][1]) + ((double)acc[k][2] + (double)acc[k][3]);
+        tot[k] += (double)((acc[k][0] + acc[k][1]) + (acc[k][2] + acc[k][3]));
         acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.0f;
     }
 }
 
-// Columns of pair item cb of the row block starting at row r0: the row
-// block's L = n - r0 columns (its part of the upper triangle) are cut into
-// m = ceil(L / W) chunks of equal width, rounded up to a multiple of 4 (the
-// b128 column reads need 16-byte alignment).  The host enumerates items with
-// the same arithmetic.
+// Columns [c0, c1) of pair item cb of the row block starting at row r0
+// (row_chunks gives the chunk width; the host enumerates items with it).
 __device__ __forceinline__ void item_columns(int64_t n, int64_t r0, int64_t W, int32_t cb,
                                              int64_t* c0, int64_t* c1) {
-    const int64_t L = n - r0;
-    const int64_t m = (L + W - 1) / W;
-    const int64_t w = (((L + m - 1) / m) + 3) & ~(int64_t)3;
+    int64_t m, w;
+    row_chunks(n, r0, W, &m, &w);
     *c0 = r0 + (int64_t)cb * w;
     *c1 = min(*c0 + w, n);
 }
@@ -334,7 +336,10 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
                                 const PolyConsts& pc, float* tile, double* red) {
     constexpr int TI = BLOCK * R;
     const double tau = centre_offset(rb);
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+    // the wave index is the same in all lanes of a wave: readfirstlane tells the
+    // compiler so, and the column loops then run on scalar counters
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int64_t n = d.n;
     const int64_t r0 = (int64_t)rb * TI;
     const int64_t wlo = r0 + (int64_t)wave * WAVE * R;
@@ -418,7 +423,10 @@ template <int RO, int R, int BLOCK>
 __device__ double pair_item_f64(const View& d, int32_t rb, int32_t cb, double mean, double scale,
                                 double* tile, double* red) {
     constexpr int TI = BLOCK * R;
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+    // the wave index is the same in all lanes of a wave: readfirstlane tells the
+    // compiler so, and the column loops then run on scalar counters
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int64_t n = d.n;
     const int64_t r0 = (int64_t)rb * TI;
     const int64_t wlo = r0 + (int64_t)wave * WAVE * R;
@@ -483,18 +491,45 @@ __device__ double pair_item_f64(const View& d, int32_t rb, int32_t cb, double me
 //   g2 = g1 (-2 K4(0) n / A6)^(1/7),  A6 = 2 S6 + n K6(0)       (Steps IV-V)
 //   h  = g2 (R(K) n / A4)^(1/5),      A4 = 2 S4 + n K4(0)       (Steps VI-VII)
 // which are the printed formulas with Psi8, Psi6(g1), Psi4(g2) substituted.
+// Values of earlier stages a finaliser needs, loaded together as soon as it
+// knows it is the finaliser.
+struct Prior {
+    int32_t status, safe;
+    double g1, g2, maxdev, mean, scale;
+};
+
+__device__ __forceinline__ Prior load_prior(State* st) {
+    Prior p;
+    p.status = ld_i32(&st->status);
+    p.safe = __hip_atomic_load(&st->safe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    p.g1 = ld_f64(&st->g1);
+    p.g2 = ld_f64(&st->g2);
+    p.maxdev = ld_f64(&st->maxdev);
+    p.mean = ld_f64(&st->mean);
+    p.scale = ld_f64(&st->scale);
+    return p;
+}
+
+// What a finaliser publishes to the items of later stages.
+struct Published {
+    int32_t status, safe;
+    double mean, scale;
+};
+
 template <int PREC>
-__device__ void finalize_stage(const View& d, State* st, int32_t stage, double tot, double aux,
-                               const PolyConsts& pc) {
+__device__ Published finalize_stage(const View& d, State* st, int32_t stage, double tot, double aux,
+                                    const Prior& pr, const PolyConsts& pc) {
     const double pi = 3.14159265358979323846;
     const double rt2pi = sqrt(2.0 * pi);
     const double K6_0 = -15.0 / rt2pi, K4_0 = 3.0 / rt2pi, RK = 1.0 / (2.0 * sqrt(pi));
     const double nd = (double)d.n;
-    int32_t status = ld_i32(&st->status);
+    int32_t status = pr.status;
+    Published out{pr.status, pr.safe, pr.mean, pr.scale};
     switch (stage) {
     case ST_SUM: {
         if (!isfinite(tot)) { set_status(st, KDE_ENONFINITE); status = KDE_ENONFINITE; }
-        st_f64(&st->mean, tot / nd);
+        out.mean = tot / nd;
+        st_f64(&st->mean, out.mean);
         break;
     }
     case ST_SSQ: {
@@ -510,10 +545,10 @@ __device__ void finalize_stage(const View& d, State* st, int32_t stage, double t
         } else {
             g = d.psi_g;
         }
-        const double scale = 1.0 / g;
-        st_f64(&st->scale, scale);
-        __hip_atomic_store(&st->safe, (int32_t)(aux * scale > kSafeLimit ? 1 : 0), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        out.scale = 1.0 / g;
+        out.safe = aux * out.scale > kSafeLimit ? 1 : 0;
+        st_f64(&st->scale, out.scale);
+        __hip_atomic_store(&st->safe, out.safe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
     }
     case ST_PSI6: {
@@ -521,16 +556,16 @@ __device__ void finalize_stage(const View& d, State* st, int32_t stage, double t
         const double S6 = (PREC == 1 ? exp2(-5.0 * (double)pc.k_hi) : 1.0) * tot / rt2pi;
         st_f64(&st->S6, S6);
         const double A6 = 2.0 * S6 + nd * K6_0;
-        const double g1 = d.mode == MODE_PLUGIN ? ld_f64(&st->g1) : d.psi_g;
+        const double g1 = d.mode == MODE_PLUGIN ? pr.g1 : d.psi_g;
         st_f64(&st->psi6, A6 / (nd * nd * pow(g1, 7.0)));
         if (d.mode == MODE_PLUGIN) {
             if (status == 0 && !(A6 < 0.0)) { set_status(st, KDE_EDEGENERATE); status = KDE_EDEGENERATE; }
             const double g2 = g1 * pow(-2.0 * K4_0 * nd / A6, 1.0 / 7.0);
             st_f64(&st->g2, g2);
-            const double scale = 1.0 / g2;
-            st_f64(&st->scale, scale);
-            __hip_atomic_store(&st->safe, (int32_t)(ld_f64(&st->maxdev) * scale > kSafeLimit ? 1 : 0),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            out.scale = 1.0 / g2;
+            out.safe = pr.maxdev * out.scale > kSafeLimit ? 1 : 0;
+            st_f64(&st->scale, out.scale);
+            __hip_atomic_store(&st->safe, out.safe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         break;
     }
@@ -538,7 +573,7 @@ __device__ void finalize_stage(const View& d, State* st, int32_t stage, double t
         const double S4 = tot / rt2pi;
         st_f64(&st->S4, S4);
         const double A4 = 2.0 * S4 + nd * K4_0;
-        const double g2 = d.mode == MODE_PLUGIN ? ld_f64(&st->g2) : d.psi_g;
+        const double g2 = d.mode == MODE_PLUGIN ? pr.g2 : d.psi_g;
         st_f64(&st->psi4, A4 / (nd * nd * pow(g2, 5.0)));
         if (d.mode == MODE_PLUGIN) {
             if (status == 0 && !(A4 > 0.0)) { set_status(st, KDE_EDEGENERATE); status = KDE_EDEGENERATE; }
@@ -549,16 +584,71 @@ __device__ void finalize_stage(const View& d, State* st, int32_t stage, double t
     default:
         break;
     }
+    out.status = status;
+    return out;
 }
 
 // --------------------------------------------------------------- kernels
-__global__ void k_init(State* states, int32_t count, uint32_t* ticket) {
+__global__ void k_init(State* states, Pub* pubs, int32_t count, uint32_t* ticket) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) {
         State s = {};
         states[i] = s;
     }
+    if (i < (int64_t)count * kPubReplicas) {
+        Pub q = {};
+        pubs[i] = q;
+    }
     if (i == 0) *ticket = 0u;
+}
+
+// Exact accumulation of pair-item partials.  A partial v with |v| < 2^62 is
+// taken as the integer V = trunc(v 2^64) (two's complement over 128 bits),
+// cut into four 32-bit limbs, the top one signed, and each limb is added
+// into its own 64-bit integer: below 2^31 additions nothing overflows, and
+// the exact total is recovered by carrying once at the end.  The truncation
+// costs at most 2^-64 per item.
+constexpr double kFxLimit = 4611686018427387904.0;  // 2^62
+
+__device__ __forceinline__ void fx_add(int64_t (&acc)[4], double v) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(v);
+    const int e = (int)((bits >> 52) & 0x7ff);
+    if (e == 0) return;  // zero or below 2^-1022: truncates to 0
+    const uint64_t mant = (bits & 0xfffffffffffffull) | (1ull << 52);
+    // v = mant 2^(e - 1075), so V = mant 2^s with s = e - 1011
+    const int sh = e - 1011;
+    uint64_t lo, hi;
+    if (sh <= -53) {
+        return;
+    } else if (sh < 0) {
+        lo = mant >> (-sh);
+        hi = 0;
+    } else if (sh == 0) {
+        lo = mant;
+        hi = 0;
+    } else if (sh < 64) {
+        lo = mant << sh;
+        hi = mant >> (64 - sh);
+    } else {
+        lo = 0;
+        hi = mant << (sh - 64);  // sh < 74 since |v| < 2^62
+    }
+    if (bits >> 63) {
+        lo = ~lo + 1ull;
+        hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+    }
+    acc[0] += (int64_t)(lo & 0xffffffffull);
+    acc[1] += (int64_t)(lo >> 32);
+    acc[2] += (int64_t)(hi & 0xffffffffull);
+    acc[3] += (int64_t)(int32_t)(uint32_t)(hi >> 32);
+}
+
+// The value of accumulated limbs, rounded to FP64.
+__device__ __forceinline__ double fx_value(const int64_t (&a)[4]) {
+    const __int128 V = ((__int128)a[3] << 96) + ((__int128)a[2] << 64) + ((__int128)a[1] << 32) + (__int128)a[0];
+    const int64_t hi = (int64_t)(V >> 64);
+    const uint64_t lo = (uint64_t)V;
+    return (double)hi + ldexp((double)lo, -64);
 }
 
 // Completion of `cnt` items of one (sample, stage) whose slots this block
@@ -566,10 +656,20 @@ __global__ void k_init(State* states, int32_t count, uint32_t* ticket) {
 // block that brings the counter to the stage's item count sums the stage's
 // slots in index order (Neumaier) and runs the stage's scalar formulas.
 template <int PREC, int BLOCK>
-__device__ void complete_items(const LaunchArgs& A, const View& d, State* st, int32_t stage, uint32_t cnt,
-                               double* red, int32_t* sh_last) {
+__device__ void complete_items(const LaunchArgs& A, int32_t ds, const View& d, State* st, int32_t stage,
+                               uint32_t cnt, int64_t (&pacc)[4], double* red, int32_t* sh_last,
+                               Published* pub) {
     const int tid = threadIdx.x;
     if (tid == 0) {
+        if (stage >= ST_PSI6) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (pacc[q] != 0)
+                    __hip_atomic_fetch_add(&st->acc[stage - ST_PSI6][q], pacc[q], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                pacc[q] = 0;
+            }
+        }
         const uint32_t old = __hip_atomic_fetch_add(&st->done[stage], cnt, __ATOMIC_RELEASE,
                                                     __HIP_MEMORY_SCOPE_AGENT);
         *sh_last = (old + cnt == (uint32_t)d.cnt) ? 1 : 0;
@@ -577,34 +677,59 @@ __device__ void complete_items(const LaunchArgs& A, const View& d, State* st, in
     __syncthreads();
     if (*sh_last) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const int64_t base = d.base;
-        const int32_t n_slots = d.cnt;
-        // each thread sums its slots k = tid + BLOCK q in q order (Neumaier),
-        // loading U of them at a time so the loads overlap
-        constexpr int U = 8;
-        double s = 0.0, c = 0.0, m = 0.0;
-        for (int32_t k0 = tid; k0 < n_slots; k0 += BLOCK * U) {
-            Slot buf[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t k = k0 + u * BLOCK;
-                buf[u] = k < n_slots ? A.slots[base + k] : Slot{0.0, 0.0};
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const double tt = s + buf[u].v;
-                c += fabs(s) >= fabs(buf[u].v) ? (s - tt) + buf[u].v : (buf[u].v - tt) + s;
-                s = tt;
-                m = fmax(m, buf[u].aux);
-            }
-        }
-        const double tot = block_sum<BLOCK>(s + c, red);
-        const double mx = block_max<BLOCK>(m, red);
+        Prior pr{};
+        int64_t a[4] = {0, 0, 0, 0};
         if (tid == 0) {
-            finalize_stage<PREC>(d, st, stage, tot, mx, A.pc);
+            pr = load_prior(st);
+            if (stage >= ST_PSI6)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    a[q] = __hip_atomic_load(&st->acc[stage - ST_PSI6][q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        double tot = 0.0, mx = 0.0;
+        if (stage < ST_PSI6) {
+            // each thread sums its slots k = tid + BLOCK q in q order
+            // (Neumaier), loading U of them at a time so the loads overlap;
+            // only Step I's second pass has an aux part
+            const int64_t base = d.base;
+            const int32_t n_slots = d.cnt;
+            constexpr int U = 8;
+            double s = 0.0, c = 0.0, m = 0.0;
+            for (int32_t k0 = tid; k0 < n_slots; k0 += BLOCK * U) {
+                double buf[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t k = k0 + u * BLOCK;
+                    buf[u] = k < n_slots ? A.slots[base + k].v : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double tt = s + buf[u];
+                    c += fabs(s) >= fabs(buf[u]) ? (s - tt) + buf[u] : (buf[u] - tt) + s;
+                    s = tt;
+                }
+            }
+            if (stage == ST_SSQ)
+                for (int32_t k = tid; k < n_slots; k += BLOCK) m = fmax(m, A.slots[base + k].aux);
+            tot = block_sum<BLOCK>(s + c, red);
+            mx = block_max<BLOCK>(m, red);
+        }
+        if (tid == 0) {
+            if (stage >= ST_PSI6) tot = fx_value(a);
+            *pub = finalize_stage<PREC>(d, st, stage, tot, mx, pr, A.pc);
             __hip_atomic_store(&st->t_fin[stage], (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             st_release(&st->ready[stage], 1u);
+        }
+        __syncthreads();
+        if (tid < kPubReplicas) {
+            // every replica gets the values, then its flag with release order
+            Pub* q = A.pubs + (int64_t)ds * kPubReplicas + tid;
+            __hip_atomic_store(&q->status, pub->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&q->safe, pub->safe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st_f64(&q->mean, pub->mean);
+            st_f64(&q->scale, pub->scale);
+            st_release(&q->ready[stage], 1u);
         }
     }
     __syncthreads();
@@ -637,6 +762,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
     __shared__ int32_t sh_status, sh_safe, sh_last, sh_flush;
     __shared__ int32_t sh_cds, sh_cwait;  // (sample, stage) whose published scalars are cached
     __shared__ double sh_mean, sh_scale;
+    __shared__ Published sh_pub;  // a finaliser's values, for its replica writers
 
     const int tid = threadIdx.x;
     uint32_t next = 0;  // thread 0: prefetched ticket
@@ -645,9 +771,12 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         sh_cds = -1;
         sh_cwait = -1;
     }
-    // finished items not yet counted (same values in every thread)
+    // finished items not yet counted (same values in every thread) and, in
+    // LDS, their exact sum if they are pair items
     int32_t pend_ds = -1, pend_stage = 0;
     uint32_t pend_cnt = 0;
+    __shared__ int64_t pacc[4];
+    if (tid < 4) pacc[tid] = 0;
     for (;;) {
         if (tid == 0) {
             sh_ticket = next;
@@ -659,8 +788,9 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         Item it = {};
         if (have) it = A.items[t];
         if (pend_cnt != 0u && (!have || it.ds != pend_ds || it.stage != pend_stage)) {
-            complete_items<PREC, BLOCK>(A, load_view(A.descs + pend_ds, pend_stage), A.states + pend_ds,
-                                        pend_stage, pend_cnt, red, &sh_last);
+            complete_items<PREC, BLOCK>(A, pend_ds, load_view(A.descs + pend_ds, pend_stage),
+                                        A.states + pend_ds, pend_stage, pend_cnt, pacc, red, &sh_last,
+                                        &sh_pub);
             pend_cnt = 0u;
         }
         if (!have) break;
@@ -676,23 +806,33 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
             if (it.wait < 0) {
                 sh_status = ld_i32(&st->status);
             } else if (sh_cds != it.ds || sh_cwait != it.wait) {
+                const Pub* q = A.pubs + (int64_t)it.ds * kPubReplicas + (blockIdx.x & (kPubReplicas - 1));
                 const uint64_t t0 = wall_clock64();
                 bool ready = true;
-                while (__hip_atomic_load(&st->ready[it.wait], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                for (uint32_t spin = 1;
+                     __hip_atomic_load(&q->ready[it.wait], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+                     ++spin) {
                     __builtin_amdgcn_s_sleep(8);
-                    if (ld_i32(&st->status) == KDE_ETIMEOUT || wall_clock64() - t0 > A.timeout_ticks) {
+                    if ((spin & 63u) == 0u &&
+                        (ld_i32(&st->status) == KDE_ETIMEOUT || wall_clock64() - t0 > A.timeout_ticks)) {
                         set_status(st, KDE_ETIMEOUT);  // keeps an earlier status if one is set
                         ready = false;
                         break;
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                sh_status = ld_i32(&st->status);
-                sh_mean = ld_f64(&st->mean);
-                sh_scale = ld_f64(&st->scale);
-                sh_safe = __hip_atomic_load(&st->safe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                sh_cds = ready ? it.ds : -1;
-                sh_cwait = ready ? it.wait : -1;
+                if (ready) {
+                    sh_status = __hip_atomic_load(&q->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    sh_mean = ld_f64(&q->mean);
+                    sh_scale = ld_f64(&q->scale);
+                    sh_safe = __hip_atomic_load(&q->safe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    sh_cds = it.ds;
+                    sh_cwait = it.wait;
+                } else {
+                    sh_status = ld_i32(&st->status);  // nonzero: the item is skipped
+                    sh_cds = -1;
+                    sh_cwait = -1;
+                }
             }
         }
         __syncthreads();
@@ -734,10 +874,17 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         }
 
         if (tid == 0) {
-            Slot s;
-            s.v = v;
-            s.aux = aux;
-            A.slots[it.slot] = s;
+            if (it.stage >= ST_PSI6) {
+                if (fabs(v) < kFxLimit)
+                    fx_add(pacc, v);
+                else if (status == 0)
+                    set_status(st, KDE_EDEGENERATE);  // non-finite or out of range partial
+            } else {
+                Slot s;
+                s.v = v;
+                s.aux = aux;
+                A.slots[it.slot] = s;
+            }
             sh_flush = next >= (uint32_t)it.run_end ? 1 : 0;
         }
         pend_ds = it.ds;
@@ -745,17 +892,18 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         ++pend_cnt;
         __syncthreads();
         if (sh_flush) {
-            complete_items<PREC, BLOCK>(A, d, st, it.stage, pend_cnt, red, &sh_last);
+            complete_items<PREC, BLOCK>(A, it.ds, d, st, it.stage, pend_cnt, pacc, red, &sh_last, &sh_pub);
             pend_cnt = 0u;
         }
     }
 }
 
 // ---------------------------------------------------------- host entry
-hipError_t launch_init(State* states, int32_t count, uint32_t* ticket, hipStream_t s) {
+hipError_t launch_init(State* states, Pub* pubs, int32_t count, uint32_t* ticket, hipStream_t s) {
     const int threads = 256;
-    const int blocks = (count + threads - 1) / threads > 0 ? (count + threads - 1) / threads : 1;
-    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(threads), 0, s, states, count, ticket);
+    const int64_t cover = (int64_t)count * kPubReplicas;
+    const int blocks = cover > 0 ? (int)((cover + threads - 1) / threads) : 1;
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(threads), 0, s, states, pubs, count, ticket);
     return hipGetLastError();
 }
 

@@ -178,17 +178,18 @@ PairGeom pair_geom(const kde_ctx* c, int64_t n) {
     return g;
 }
 
-// Row block rb's columns [rb TI, n) are cut into equal chunks of at most W
-// (rounded up to a multiple of 4); the device computes the same widths.
+// Row block rb's columns [rb TI, n) in chunks (row_chunks; the device
+// computes the same widths).
 int64_t pair_items_in_row(const PairGeom& g, int64_t rb) {
-    const int64_t cols = g.n - rb * g.TI;
-    return cols > 0 ? (cols + g.W - 1) / g.W : 0;
+    int64_t m, w;
+    row_chunks(g.n, rb * g.TI, g.W, &m, &w);
+    return m;
 }
 
 int64_t pair_chunk_width(const PairGeom& g, int64_t rb) {
-    const int64_t L = g.n - rb * g.TI;
-    const int64_t m = (L + g.W - 1) / g.W;
-    return (((L + m - 1) / m) + 3) & ~(int64_t)3;
+    int64_t m, w;
+    row_chunks(g.n, rb * g.TI, g.W, &m, &w);
+    return w;
 }
 
 int64_t pair_item_count(const PairGeom& g) {
@@ -329,6 +330,7 @@ int total_plan_bytes(const kde_ctx* c, size_t extra, size_t* out) {
 int upload_plan(kde_ctx* c, Plan& p) {
     const size_t need = sizeof(Item) * std::max<size_t>(1, p.items.size()) +
                         sizeof(Desc) * std::max(1, p.count) + sizeof(State) * std::max(1, p.count) +
+                        sizeof(Pub) * kPubReplicas * std::max(1, p.count) +
                         sizeof(Slot) * (size_t)std::max<int64_t>(1, p.n_slots) + 256;
     if (c->mem_budget > 0) {
         size_t have = 0;
@@ -344,6 +346,7 @@ int upload_plan(kde_ctx* c, Plan& p) {
     if ((st = p.d_items.ensure(sizeof(Item) * std::max<size_t>(1, p.items.size()), "work list"))) return st;
     if ((st = p.d_descs.ensure(sizeof(Desc) * std::max(1, p.count), "descriptors"))) return st;
     if ((st = p.d_states.ensure(sizeof(State) * std::max(1, p.count), "states"))) return st;
+    if ((st = p.d_pubs.ensure(sizeof(Pub) * kPubReplicas * std::max(1, p.count), "published scalars"))) return st;
     if ((st = p.d_slots.ensure(sizeof(Slot) * (size_t)std::max<int64_t>(1, p.n_slots), "slots"))) return st;
     if ((st = p.d_ticket.ensure(256, "ticket"))) return st;
     HIPCHK(hipHostMalloc((void**)&p.h_states, sizeof(State) * std::max(1, p.count), hipHostMallocDefault));
@@ -362,6 +365,7 @@ LaunchArgs args_for(const kde_ctx* c, Plan& p) {
     a.descs = (const Desc*)p.d_descs.p;
     a.states = (State*)p.d_states.p;
     a.slots = (Slot*)p.d_slots.p;
+    a.pubs = (Pub*)p.d_pubs.p;
     a.ticket = (uint32_t*)p.d_ticket.p;
     a.pc = c->pc;
     a.timeout_ticks = kTimeoutTicks;
@@ -377,7 +381,7 @@ int run_plan(kde_ctx* c, Plan& p, hipStream_t s) {
         hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             const LaunchArgs a = args_for(c, p);
-            hipError_t e1 = launch_init((State*)p.d_states.p, p.count, (uint32_t*)p.d_ticket.p, cap);
+            hipError_t e1 = launch_init((State*)p.d_states.p, (Pub*)p.d_pubs.p, p.count, (uint32_t*)p.d_ticket.p, cap);
             hipError_t e2 = launch_persistent(c->precision, c->R, p.grid, cap, a);
             e = hipStreamEndCapture(cap, &graph);
             if (e == hipSuccess && (e1 != hipSuccess || e2 != hipSuccess)) e = e1 != hipSuccess ? e1 : e2;

@@ -2,11 +2,37 @@
 // libkdeplugin.  Not part of the public interface.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "kdeplugin.h"
 
 namespace kde {
+
+// Column chunks of a pair stage.  The row block starting at row r0 owns the
+// columns [r0, n) of the upper triangle, L = n - r0 of them, and cuts them
+// into m = ceil(L / Wr) chunks of equal width w (rounded up to a multiple of
+// 4 for the b128 column reads).  Wr is the stage's chunk width W for row
+// blocks with L > n/2, W/2 for n/4 < L <= n/2 and W/4 below (not under
+// min(W, 256)): the work list runs row blocks in increasing order, so the
+// last quarter of a stage's pairs comes in smaller items and the blocks of
+// the device run out of work at nearly the same time.  Host and device
+// compute the chunks with this one function.
+__host__ __device__ inline void row_chunks(int64_t n, int64_t r0, int64_t W, int64_t* m, int64_t* w) {
+    const int64_t L = n - r0;
+    if (L <= 0) {
+        *m = 0;
+        *w = 0;
+        return;
+    }
+    int64_t Wr = W;
+    if (2 * L <= n) Wr >>= 1;
+    if (4 * L <= n) Wr >>= 1;
+    const int64_t lo = W < 256 ? W : 256;
+    if (Wr < lo) Wr = lo;
+    *m = (L + Wr - 1) / Wr;
+    *w = (((L + *m - 1) / *m) + 3) & ~(int64_t)3;
+}
 
 // Stages of one bandwidth selection, in dependency order (Algorithm 1).
 enum Stage : int32_t {
@@ -67,7 +93,25 @@ struct State {
     double maxdev;               // max |x - mean|
     uint64_t t_first;            // wall clock (100 MHz ticks) when the first item started
     uint64_t t_fin[NUM_STAGES];  // wall clock when each stage's finaliser published
+    // Exact sums of the pair stages' item partials (Steps IV and VI) in fixed
+    // point, units of 2^-64, as four 32-bit limbs added in 64-bit integers
+    int64_t acc[2][4];
 };
+
+// Replicated copy of the scalars a stage's finaliser publishes for the items
+// of later stages.  Each sample has kPubReplicas of them, one 128-byte line
+// each; block b waits on and reads replica b mod kPubReplicas, so the blocks
+// of the device do not all poll and load one line at a stage boundary.
+constexpr int kPubReplicas = 16;
+struct alignas(128) Pub {
+    uint32_t ready[NUM_STAGES];  // 1 once the stage's finaliser has published
+    int32_t status;
+    int32_t safe;
+    double mean;
+    double scale;
+    uint8_t pad[88];
+};
+static_assert(sizeof(Pub) == 128, "Pub layout");
 
 // Partial result of one work item.
 struct Slot {
@@ -89,6 +133,7 @@ struct LaunchArgs {
     const Desc* descs;
     State* states;
     Slot* slots;
+    Pub* pubs;               // kPubReplicas per sample
     uint32_t* ticket;
     PolyConsts pc;
     uint64_t timeout_ticks;  // wall-clock ticks (100 MHz) an in-kernel wait may take

@@ -14,7 +14,7 @@
 #include "kde_internal.h"
 
 namespace kde {
-hipError_t launch_init(State* states, int32_t count, uint32_t* ticket, hipStream_t s);
+hipError_t launch_init(State* states, Pub* pubs, int32_t count, uint32_t* ticket, hipStream_t s);
 hipError_t launch_persistent(int prec, int R, int grid, hipStream_t s, const LaunchArgs& a);
 hipError_t persistent_occupancy(int prec, int R, int* blocks_per_cu);
 }  // namespace kde
@@ -57,7 +57,7 @@ struct Plan {
     std::vector<Item> items;
     std::vector<Desc> descs;          // host copy of what is on the device
     bool descs_valid = false;
-    DevBuf d_items, d_descs, d_states, d_slots, d_ticket;
+    DevBuf d_items, d_descs, d_states, d_pubs, d_slots, d_ticket;
     State* h_states = nullptr;        // pinned
     int64_t n_slots = 0;
     hipGraphExec_t exec = nullptr;
@@ -67,7 +67,7 @@ struct Plan {
         if (h_states) (void)hipHostFree(h_states);
     }
     size_t device_bytes() const {
-        return d_items.bytes + d_descs.bytes + d_states.bytes + d_slots.bytes + d_ticket.bytes;
+        return d_items.bytes + d_descs.bytes + d_states.bytes + d_pubs.bytes + d_slots.bytes + d_ticket.bytes;
     }
 };
 

@@ -110,7 +110,7 @@ struct kde_server {
     kde_ctx* ctx = nullptr;
     kde_server_options opt{};
     hipStream_t stream = nullptr, copy_stream = nullptr;
-    DevBuf arena_buf, d_descs, d_states, d_items[2], d_ticket;
+    DevBuf arena_buf, d_descs, d_states, d_pubs, d_items[2], d_ticket;
     std::unique_ptr<Arena> arena;
     Desc* h_descs = nullptr;          // pinned mirrors
     State* h_states[2] = {nullptr, nullptr};  // state read-back of the steps using list buffer 0 / 1
@@ -186,6 +186,8 @@ int admit_one(kde_server* s, std::unique_ptr<Request>& rp) {
     HIPCHK(hipMemcpyAsync((Desc*)s->d_descs.p + r.slot, s->h_descs + r.slot, sizeof(Desc), hipMemcpyHostToDevice,
                           s->stream));
     HIPCHK(hipMemsetAsync((State*)s->d_states.p + r.slot, 0, sizeof(State), s->stream));
+    HIPCHK(hipMemsetAsync((Pub*)s->d_pubs.p + (size_t)r.slot * kPubReplicas, 0, sizeof(Pub) * kPubReplicas,
+                          s->stream));
     r.t_admit = now_ms();
     return KDE_OK;
 }
@@ -336,6 +338,7 @@ int launch_step(kde_server* s) {
     a.descs = (const Desc*)s->d_descs.p;
     a.states = (State*)s->d_states.p;
     a.slots = (Slot*)s->arena_buf.p;
+    a.pubs = (Pub*)s->d_pubs.p;
     a.ticket = ticket;
     a.pc = s->ctx->pc;
     a.timeout_ticks = kTimeoutTicks;
@@ -429,6 +432,8 @@ int kde_server_create(kde_server** out, kde_ctx* ctx, const kde_server_options* 
     if ((st = s->arena_buf.ensure((size_t)o.mem_budget, "server arena"))) return st;
     if ((st = s->d_descs.ensure(sizeof(Desc) * (size_t)o.max_active, "server descriptors"))) return st;
     if ((st = s->d_states.ensure(sizeof(State) * (size_t)o.max_active, "server states"))) return st;
+    if ((st = s->d_pubs.ensure(sizeof(Pub) * kPubReplicas * (size_t)o.max_active, "server published scalars")))
+        return st;
     if ((st = s->d_ticket.ensure(512, "server tickets"))) return st;
     s->arena = std::make_unique<Arena>((size_t)o.mem_budget);
     HIPCHK(hipHostMalloc((void**)&s->h_descs, sizeof(Desc) * (size_t)o.max_active, hipHostMallocDefault));
