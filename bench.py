@@ -33,7 +33,9 @@ sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3      # MI355X datasheet, packed FP32 vector
 FP32_NONPACKED_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+FP64_VECTOR_PEAK_TFLOPS = 78.6       # MI355X datasheet, FP64 vector
 FLOP_PER_PAIR = {6: 10, 4: 8}
+EVAL_FLOP_PER_PAIR = 4            # density evaluation: sub, square, exp2, add
 
 WORKLOADS = {
     "normal1024": dict(desc="single dataset n=1024, N(0,1), seed 0", n=1024, kind="normal", seed=0),
@@ -164,6 +166,66 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def bench_eval(args):
+    """Density evaluation (equation (1)) with the selected bandwidth: the
+    n = 2^20 lognormal workload sample on a grid of 4096 points spanning its
+    0.1% to 99.9% quantiles; one step = one evaluation of all 4096 points
+    (n m pair evaluations), sample and grid resident in HBM."""
+    import numpy as np
+    import torch
+    from paper_1505_02100_amd import kdeplugin as kp
+    from paper_1505_02100_amd import synth
+    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp64": kp.KDE_FP64_PLAIN}
+    x = synth.workload_single_lognormal(1 << 20, 2)
+    n, m = x.size, 4096
+    xd = torch.from_numpy(x).cuda()
+    ctx = kp.Context(prec[args.precision])
+    h = ctx.plugin_bandwidth(xd).h
+    y = np.linspace(np.quantile(x, 0.001), np.quantile(x, 0.999), m)
+    yd = torch.from_numpy(y).cuda()
+    for _ in range(max(1, args.warmup)):
+        ctx.eval(xd, yd, h)
+    torch.cuda.synchronize()
+    dev = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f = ctx.eval(xd, yd, h)
+        dev.append(ctx.last_device_ms())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = (t1 - t0) / args.steps
+    dev_ms = float(np.mean(dev))
+    pairs = n * m
+    achieved = EVAL_FLOP_PER_PAIR * pairs / (dev_ms * 1e-3) / 1e12
+    out = {"metric": "pair-evals/s & %FP32 VALU peak; selections/s, p50/p99 latency vs FP64 plain",
+           "value": pairs / per, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(per * 1e3, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+           "config": {"workload": "density evaluation f(y; h) on a 4096-point grid for the n=2^20 "
+                                  "lognormal sample (1e3*exp(Z)-5e2, seed 2) with its selected h",
+                      "n": n, "m": m, "h": h, "precision": args.precision},
+           "device_ms": {q: round(float(np.percentile(dev, p)), 4) for q, p in (("p10", 10), ("p50", 50), ("p90", 90))},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                        "kernel": "kde::eval::k_eval", "kernel_ms_avg": round(dev_ms, 4),
+                        "flop_per_launch": EVAL_FLOP_PER_PAIR * pairs}}
+    if not args.no_cpu_baseline:
+        import oracle
+        k = 64
+        pick = np.linspace(0, m - 1, k).astype(int)
+        a = time.perf_counter()
+        ref = oracle.kde_eval(x, h, y[pick])
+        b = time.perf_counter()
+        got = f.cpu().numpy()[pick]
+        out["cpu_baseline"] = {"value": n * k / (b - a), "unit": "pair-evals/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{k} of the {m} grid points against all n samples ({b - a:.2f} s)"}
+        out["max_rel_err_vs_oracle"] = float(np.max(np.abs(got - ref) / ref))
+    ctx.close()
+    print(json.dumps(out))
+
+
 def bench_serve(args):
     """Poisson arrivals (rate args.rate per s for args.duration s), n log-uniform
     in [1e3, 4e6], normal / bimodal / t3 mixed, samples drawn in device memory,
@@ -228,7 +290,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["fp32", "fp32x", "fp64"], default="fp32")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch512", "serve"], default="bimodal65536")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch512", "serve", "eval4096"],
+                    default="bimodal65536")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window in seconds")
     ap.add_argument("--policy", choices=["fcfs", "sjf"], default="fcfs", help="serve: admission order")
@@ -258,6 +321,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "eval4096":
+        bench_eval(args)
         return
 
     from paper_1505_02100_amd import kdeplugin as kp
@@ -307,7 +373,10 @@ def main():
                       "n": n, "precision": args.precision, "pairs_per_selection": pairs,
                       "tile": cfg},
            "selections_per_s": round(1e3 / ms_per_step, 3),
+           "device_ms_per_selection": {q: round(float(np.percentile(dev_ms, p)), 4)
+                                       for q, p in (("p10", 10), ("p50", 50), ("p90", 90))},
            "stage_timeline_ms": [round(t, 4) for t in timeline],
+           "exp2_per_s_device": pairs / (dev_ms_avg * 1e-3),
            "roofline": roofline}
 
     if not args.no_fp64_compare and args.precision != "fp64":
@@ -315,14 +384,20 @@ def main():
         ctx64.plugin_bandwidth(xd)
         k64 = max(3, args.steps // 10)
         torch.cuda.synchronize()
+        dev64 = []
         a = time.perf_counter()
         for _ in range(k64):
             r64 = ctx64.plugin_bandwidth(xd)
+            dev64.append(ctx64.last_device_ms())
         torch.cuda.synchronize()
         b = time.perf_counter()
+        ach64 = flop / (float(np.mean(dev64)) * 1e-3) / 1e12
         out["fp64_plain"] = {"pair_evals_per_s": pairs / ((b - a) / k64),
                              "selections_per_s": round(k64 / (b - a), 3),
                              "ms_per_step": round((b - a) * 1e3 / k64, 4),
+                             "kernel_ms_avg": round(float(np.mean(dev64)), 4),
+                             "achieved_tflops": round(ach64, 3),
+                             "frac_of_fp64_peak": round(ach64 / FP64_VECTOR_PEAK_TFLOPS, 4),
                              "speedup_of_measured_path": round(value / (pairs / ((b - a) / k64)), 3),
                              "rel_diff_h": abs(res.h - r64.h) / r64.h}
         ctx64.close()
@@ -339,6 +414,21 @@ def main():
                                          f"({pairs} pair evaluations, {b - a:.2f} s)"}
         out["rel_err_vs_oracle"] = {k: abs(getattr(res, k) - getattr(ref, k)) / abs(getattr(ref, k))
                                     for k in ("h", "psi6", "psi4", "g2")}
+        # one host core on a bounded part of the same work: the Step IV pair sum
+        # of the first rows against all later columns, at the selection's g1
+        rows = max(1, min(n, (1 << 26) // max(1, n)))
+        oracle.set_num_threads(1)
+        try:
+            a = time.perf_counter()
+            oracle.block_sum(x, 6, ref.g1, 0, rows, 0, n)
+            b = time.perf_counter()
+        finally:
+            oracle.set_num_threads(threads)
+        p1 = sum(n - 1 - i for i in range(rows))
+        out["cpu_baseline_1core"] = {"value": p1 / (b - a), "unit": "pair-evals/s", "cores": 1,
+                                     "kind": "oracle",
+                                     "sample": f"Step IV pair sum of rows 0..{rows - 1} against all later "
+                                               f"columns ({p1} pair evaluations, {b - a:.2f} s)"}
     ctx.close()
     print(json.dumps(out))
 

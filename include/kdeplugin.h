@@ -72,9 +72,10 @@ extern "C" {
 #define KDE_FP64_PLAIN 0 /* pair sums in FP64 with the printed polynomials and FP64 exp      */
 #define KDE_FP32_KAHAN 1 /* pair terms in FP32 (exp2 on the transcendental unit, Hermite
                             factors in y^2 with exact integer coefficients), compensated
-                            per-thread sums (FP32 accumulators of at most 4 terms folded
-                            into FP64); moments, cross-block reductions and Steps I-III,
-                            V, VII in FP64.  The one systematic error left by
+                            per-thread sums (FP32 accumulators of at most 4 terms, added
+                            pairwise in FP32 and folded into FP64); moments, cross-block
+                            sums (exact, in fixed point) and Steps I-III, V, VII in
+                            FP64.  The one systematic error left by
                             construction is the FP32 rounding of log2(e)/2 (relative
                             1.3e-8) in the exponent                                       */
 #define KDE_FP32_KAHAN_EXACT 2 /* as KDE_FP32_KAHAN with log2(e)/2 carried as two FP32
@@ -203,6 +204,32 @@ KDE_API int kde_psi_item_geometry(const kde_ctx* ctx, int64_t n, int64_t item, i
 KDE_API int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r,
                   double g, int64_t item_begin, int64_t item_end, kde_stream stream,
                   double* partial);
+
+/* ------------------------------------------------------ density evaluation */
+
+/* The kernel density estimate of equation (1) with the Gaussian kernel of
+ * equation (2), for a bandwidth h (for example the one kde_plugin_bandwidth
+ * selected):
+ *     out[k] = (n h)^-1 sum_i phi((y[k] - x[i]) / h),    k = 0 .. m-1,
+ * on a grid of points or at the samples themselves.
+ *   x, n, mem_kind, dtype: the n >= 1 samples, as for the other calls.
+ *   y, m: m >= 0 evaluation points (FP64); out: m FP64 results.  y and out
+ *     are both host memory (y_mem_kind = KDE_MEM_HOST) or both device memory
+ *     on the context's GPU (KDE_MEM_DEVICE).
+ *   Precision from the context: KDE_FP64_PLAIN evaluates the definition in
+ *     FP64; the FP32 precisions form the scaled differences, the exp2 and
+ *     sums of at most 16 terms in FP32 (centred per tile of 256 points; a
+ *     tile whose points spread over more than about 9 h takes the
+ *     differences in FP64) and add the sums in FP64: relative error per
+ *     point below 1e-5.  Results are deterministic.
+ *   Errors: KDE_EINVAL (null pointer, n < 1, m < 0, h not finite and
+ *     positive, bad enum), KDE_ENONFINITE (NaN or Inf among x or y; out is
+ *     then undefined), KDE_ENOMEM, KDE_EDEVICE.  Synchronous. */
+KDE_API int kde_eval_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, const double* y,
+                        int64_t m, int y_mem_kind, double h, kde_stream stream, double* out);
+
+/* kde_eval_ex on host arrays with the process-wide default context (FP64). */
+KDE_API int kde_eval(const double* x, int64_t n, const double* y, int64_t m, double h, double* out);
 
 /* ----------------------------------------------------------------- server */
 

@@ -1,0 +1,33 @@
+// Density evaluation kernels of libkdeplugin (internal interface between the
+// host runtime and kde_eval.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kde {
+namespace eval {
+
+struct EvalArgs {
+    const void* x;     // samples on the device
+    int64_t n;
+    int32_t dtype;     // 0: FP64, 1: FP32 samples
+    int32_t prec;      // 0: FP64 plain, 1: FP32 pair arithmetic
+    const double* y;   // evaluation points on the device
+    int64_t m;
+    double h;          // bandwidth
+    double s;          // sqrt(log2(e) / 2) / h
+    double norm;       // 1 / (n h sqrt(2 pi))
+    int64_t W;         // columns per chunk (multiple of 16)
+    int32_t n_rt;      // tiles of 256 points
+    int32_t n_cc;      // column chunks
+    double* part;      // n_cc x m partial sums (n_cc > 1)
+    double* out;       // m results on the device
+    int32_t* flag;     // set to 1 when a non-finite sample or point is read
+};
+
+// Enqueue the evaluation (and the chunk reduction when n_cc > 1) on s.
+hipError_t launch(const EvalArgs& a, hipStream_t s);
+
+}  // namespace eval
+}  // namespace kde

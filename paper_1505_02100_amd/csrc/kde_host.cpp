@@ -19,6 +19,7 @@
 #include <string>
 #include <vector>
 
+#include "kde_eval.h"
 #include "kde_runtime.h"
 
 using namespace kde;
@@ -320,7 +321,7 @@ int grid_for(const kde_ctx* c, int64_t work) {
 }
 
 int total_plan_bytes(const kde_ctx* c, size_t extra, size_t* out) {
-    size_t tot = extra + c->x_stage.bytes;
+    size_t tot = extra + c->x_stage.bytes + c->ev_y.bytes + c->ev_out.bytes + c->ev_part.bytes + c->ev_flag.bytes;
     for (auto& p : c->plans) tot += p->device_bytes();
     *out = tot;
     return KDE_OK;
@@ -791,6 +792,89 @@ double kde_plugin_bandwidth(const double* x, int64_t n) {
     kde_result r;
     if (kde_plugin_bandwidth_ex(c, x, n, KDE_MEM_HOST, KDE_F64, nullptr, &r) != KDE_OK) return NAN;
     return r.h;
+}
+
+// Density evaluation (equation (1)): see kde_eval.hip for the kernels.
+int kde_eval_ex(kde_ctx* c, const void* x, int64_t n, int mem_kind, int dtype, const double* y, int64_t m,
+                int y_mem_kind, double h, kde_stream stream, double* out) {
+    if (!c) return set_err(KDE_EINVAL, "null context");
+    int st = check_x(x, n, 1, mem_kind, dtype);
+    if (st) return st;
+    if (m < 0) return set_err(KDE_EINVAL, "m must not be negative");
+    if (m > ((int64_t)1 << 31) - 1) return set_err(KDE_EINVAL, "m must be below 2^31");
+    if (y_mem_kind != KDE_MEM_HOST && y_mem_kind != KDE_MEM_DEVICE) return set_err(KDE_EINVAL, "bad y_mem_kind");
+    if (!(std::isfinite(h) && h > 0.0)) return set_err(KDE_EINVAL, "h must be finite and positive");
+    if (m == 0) return ok();
+    if (!y || !out) return set_err(KDE_EINVAL, "null evaluation point or output pointer");
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard dg(c->device);
+
+    // tiles of 256 points times chunks of W samples: at least ~4096 items, at
+    // most 2^24 pairs per item, chunks of at least 1024 samples
+    eval::EvalArgs a{};
+    a.n = n;
+    a.m = m;
+    a.dtype = dtype == KDE_F64 ? 0 : 1;
+    a.prec = c->precision == KDE_FP64_PLAIN ? 0 : 1;
+    a.h = h;
+    a.s = std::sqrt(0.5 * 1.4426950408889634) / h;
+    a.norm = 1.0 / ((double)n * h * std::sqrt(2.0 * 3.14159265358979323846));
+    const int64_t n_rt = (m + 255) / 256;
+    int64_t n_cc = std::max<int64_t>((4096 + n_rt - 1) / n_rt, (256 * n + ((int64_t)1 << 24) - 1) >> 24);
+    n_cc = std::max<int64_t>(1, std::min<int64_t>(n_cc, (n + 1023) / 1024));
+    a.W = ((((n + n_cc - 1) / n_cc) + 15) / 16) * 16;
+    n_cc = (n + a.W - 1) / a.W;
+    if (n_rt * n_cc > ((int64_t)1 << 31) - 1) return set_err(KDE_EINVAL, "too many evaluation items");
+    a.n_rt = (int32_t)n_rt;
+    a.n_cc = (int32_t)n_cc;
+
+    // device buffers (budget-checked like the work lists)
+    const size_t ybytes = (size_t)m * 8, pbytes = n_cc > 1 ? (size_t)n_cc * (size_t)m * 8 : 0;
+    const size_t xbytes = mem_kind == KDE_MEM_HOST ? (size_t)n * (dtype == KDE_F64 ? 8 : 4) : 0;
+    if (c->mem_budget > 0) {
+        size_t have = 0;
+        const size_t grow = std::max(xbytes, c->x_stage.bytes) - c->x_stage.bytes +
+                            (y_mem_kind == KDE_MEM_HOST ? 2 * ybytes : 0) + pbytes + 256;
+        total_plan_bytes(c, grow, &have);
+        if (have > (size_t)c->mem_budget)
+            return set_err(KDE_ENOMEM, "density evaluation buffers exceed the context's memory budget");
+    }
+    const void* dx = nullptr;
+    if ((st = stage_x(c, x, n, mem_kind, dtype, s, &dx))) return st;
+    a.x = dx;
+    if (y_mem_kind == KDE_MEM_HOST) {
+        if ((st = c->ev_y.ensure(ybytes, "evaluation points"))) return st;
+        if ((st = c->ev_out.ensure(ybytes, "evaluation output"))) return st;
+        HIPCHK(hipMemcpyAsync(c->ev_y.p, y, ybytes, hipMemcpyHostToDevice, s));
+        a.y = (const double*)c->ev_y.p;
+        a.out = (double*)c->ev_out.p;
+    } else {
+        a.y = y;
+        a.out = out;
+    }
+    if (pbytes && (st = c->ev_part.ensure(pbytes, "evaluation partial sums"))) return st;
+    a.part = (double*)c->ev_part.p;
+    if ((st = c->ev_flag.ensure(256, "evaluation flag"))) return st;
+    a.flag = (int32_t*)c->ev_flag.p;
+    HIPCHK(hipMemsetAsync(a.flag, 0, sizeof(int32_t), s));
+    HIPCHK(hipEventRecord(c->ev0, s));
+    HIPCHK(eval::launch(a, s));
+    HIPCHK(hipEventRecord(c->ev1, s));
+    int32_t flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, a.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (y_mem_kind == KDE_MEM_HOST) HIPCHK(hipMemcpyAsync(out, a.out, ybytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = -1.0f;
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_device_ms = ms;
+    if (flag) return set_err(KDE_ENONFINITE, "NaN or Inf among the samples or evaluation points");
+    return ok();
+}
+
+int kde_eval(const double* x, int64_t n, const double* y, int64_t m, double h, double* out) {
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    kde_ctx* c = default_ctx();
+    if (!c) return last_error_code() ? last_error_code() : KDE_EDEVICE;
+    return kde_eval_ex(c, x, n, KDE_MEM_HOST, KDE_F64, y, m, KDE_MEM_HOST, h, nullptr, out);
 }
 
 }  // extern "C"

@@ -122,6 +122,7 @@ struct kde_ctx {
     std::list<std::unique_ptr<kde::rt::Plan>> plans;  // most recently used first
     size_t max_plans = 16;
     kde::rt::DevBuf x_stage;                  // host samples copied here
+    kde::rt::DevBuf ev_y, ev_out, ev_part, ev_flag;  // density evaluation buffers
 };
 
 namespace kde {

@@ -159,6 +159,9 @@ _sig("kde_autotune", ctypes.c_int, ctypes.POINTER(kde_options), _PI64, _I32, _I3
 _sig("kde_psi_item_geometry", ctypes.c_int, _P, _I64, _I64, _PI64, _PI64, _PI64, _PI64)
 _sig("kde_psi_range", ctypes.c_int, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D,
      _I64, _I64, _P, ctypes.POINTER(_D))
+_sig("kde_eval_ex", ctypes.c_int, _P, _P, _I64, ctypes.c_int, ctypes.c_int, _P, _I64, ctypes.c_int, _D, _P,
+     _P)
+_sig("kde_eval", ctypes.c_int, ctypes.POINTER(_D), _I64, ctypes.POINTER(_D), _I64, _D, ctypes.POINTER(_D))
 
 
 def kde_version() -> str:
@@ -348,6 +351,39 @@ def kde_psi_range(ctx: int, x, r: int, g: float, item_begin: int, item_end: int)
     return out.value
 
 
+def kde_eval(x, y, h: float) -> np.ndarray:
+    """Density estimate (equation (1)) at the points y on the default FP64
+    context (host arrays)."""
+    a = _host_f64(x)
+    b = _host_f64(y)
+    out = np.empty_like(b)
+    _check(_lib.kde_eval(a.ctypes.data_as(ctypes.POINTER(_D)), a.size, b.ctypes.data_as(ctypes.POINTER(_D)),
+                         b.size, float(h), out.ctypes.data_as(ctypes.POINTER(_D))), "kde_eval")
+    return out
+
+
+def kde_eval_ex(ctx: int, x, y, h: float):
+    """Density estimate at the points y.  A CUDA float64 tensor y gives a CUDA
+    tensor result (device path, on the current stream of y's device);
+    anything else is taken as host points and gives a numpy array."""
+    s = _Samples(x)
+    if _is_torch(y) and y.device.type == "cuda":
+        torch = _torch()
+        yy = y.contiguous()
+        if yy.dtype != torch.float64:
+            raise TypeError("evaluation points must be float64")
+        out = torch.empty_like(yy)
+        stream = torch.cuda.current_stream(yy.device).cuda_stream
+        _check(_lib.kde_eval_ex(ctx, s.ptr, s.n, s.mem, s.dtype, yy.data_ptr(), yy.numel(), KDE_MEM_DEVICE,
+                                float(h), stream, out.data_ptr()), "kde_eval_ex")
+        return out
+    b = _host_f64(y)
+    out = np.empty_like(b)
+    _check(_lib.kde_eval_ex(ctx, s.ptr, s.n, s.mem, s.dtype, b.ctypes.data, b.size, KDE_MEM_HOST, float(h),
+                            s.stream, out.ctypes.data), "kde_eval_ex")
+    return out
+
+
 def kde_server_options_init() -> kde_server_options:
     o = kde_server_options()
     _lib.kde_server_options_init(ctypes.byref(o))
@@ -456,6 +492,9 @@ class Context:
 
     def psi_item_geometry(self, n, item):
         return kde_psi_item_geometry(self.handle, n, item)
+
+    def eval(self, x, y, h):
+        return kde_eval_ex(self.handle, x, y, h)
 
     def psi_range(self, x, r, g, b, e):
         return kde_psi_range(self.handle, x, r, g, b, e)

@@ -52,6 +52,7 @@ def test_host_only_entry_points():
     assert kp.kde_last_error() == kp.KDE_EINVAL
     res = kp.kde_result()
     assert kp._lib.kde_plugin_bandwidth_ex(None, None, 5, 0, 0, None, ctypes.byref(res)) == kp.KDE_EINVAL
+    assert kp._lib.kde_eval_ex(None, None, 5, 0, 0, None, 3, 0, 0.5, None, None) == kp.KDE_EINVAL
 
 
 def test_binding_names_match_the_header():

@@ -1,0 +1,133 @@
+"""Density evaluation (equation (1) with the kernel of equation (2)) on the
+GPU against the oracle's plain FP64 definition, through the C ABI.
+
+Tolerances.  FP64: both sides add n positive terms, so each is within
+(n - 1) u of the exact sum (u = 2^-53); the test allows 2 n u.  FP32: the
+relative error of a term 2^(-d^2) with d = v_y - v_x is about
+2 ln2 |d| |delta d|, where delta d is the FP32 rounding of the centred scaled
+values (at most 2^-24 (|v_y| + |v_x| + |d|), |v_y| <= 4 in a narrow tile);
+over the terms that matter (|d| <= 5) this stays below 1e-5, and the sums of
+positive terms add a few 2^-24.  Points where the density is below 1e-30 of
+its maximum (terms below FP32's range) are not compared.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_02100_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def kp():
+    from paper_1505_02100_amd import kdeplugin
+    return kdeplugin
+
+
+@pytest.fixture(scope="module")
+def ctxs(kp):
+    c = {p: kp.Context(p) for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_KAHAN)}
+    yield c
+    for v in c.values():
+        v.close()
+
+
+def _compare(got, ref, tol):
+    keep = ref > 1e-30 * ref.max()
+    rel = np.abs(got[keep] - ref[keep]) / ref[keep]
+    assert rel.max() <= tol, (rel.max(), int(np.argmax(rel)))
+    return rel.max()
+
+
+@pytest.mark.parametrize("n,m", [(1, 5), (2, 1), (1000, 77), (70000, 1000), (4099, 257)])
+def test_grid_against_oracle(kp, ctxs, n, m):
+    x = synth.bimodal(n, 11 + n)
+    h = 0.3 if n < 10 else 1.06 * x.std() * n ** -0.2
+    y = np.linspace(x.min() - 3 * h, x.max() + 3 * h, m)
+    ref = oracle.kde_eval(x, h, y)
+    _compare(ctxs[kp.KDE_FP64_PLAIN].eval(x, y, h), ref, 2 * n * U + 4 * U)
+    _compare(ctxs[kp.KDE_FP32_KAHAN].eval(x, y, h), ref, FP32_TOL)
+
+
+def test_at_the_samples_unsorted_and_sorted(kp, ctxs):
+    # unsorted points spread each tile over the whole range (FP64 differences);
+    # sorted points give narrow tiles (FP32 centred path); both within FP32_TOL
+    x = synth.draw("t3", 6000, 21)
+    h = 0.2
+    for y in (x[:3000].copy(), np.sort(x[:3000])):
+        ref = oracle.kde_eval(x, h, y)
+        _compare(ctxs[kp.KDE_FP64_PLAIN].eval(x, y, h), ref, 2 * x.size * U + 4 * U)
+        _compare(ctxs[kp.KDE_FP32_KAHAN].eval(x, y, h), ref, FP32_TOL)
+
+
+def test_device_path_equals_host_path_and_is_deterministic(kp, ctxs):
+    import torch
+    x = synth.normal(50000, 3)
+    y = np.linspace(-5, 5, 3000)
+    for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_KAHAN):
+        host = ctxs[p].eval(x, y, 0.12)
+        dev = ctxs[p].eval(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), 0.12)
+        assert isinstance(dev, torch.Tensor) and dev.is_cuda
+        assert np.array_equal(dev.cpu().numpy(), host)
+        assert np.array_equal(ctxs[p].eval(x, y, 0.12), host)
+    # float32 samples: same definition on the widened values
+    x32 = x.astype(np.float32)
+    ref = oracle.kde_eval(x32.astype(np.float64), 0.12, y)
+    _compare(ctxs[kp.KDE_FP32_KAHAN].eval(x32, y, 0.12), ref, FP32_TOL)
+
+
+def test_integrates_to_one(kp, ctxs):
+    x = synth.draw("bimodal", 20000, 4)
+    h = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth(x).h
+    y = np.linspace(x.min() - 10 * h, x.max() + 10 * h, 20001)
+    f = ctxs[kp.KDE_FP32_KAHAN].eval(x, y, h)
+    assert abs(np.trapezoid(f, y) - 1.0) < 1e-6
+
+
+def test_full_size_lognormal_grid_sampled(kp, ctxs):
+    # n = 2^20 workload sample, its selected h, a 4096-point grid: sampled points
+    # against the oracle (O(n) each)
+    import torch
+    x = synth.workload_single_lognormal(1 << 20, 2)
+    xd = torch.from_numpy(x).cuda()
+    h = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth(xd).h
+    y = np.linspace(np.quantile(x, 0.001), np.quantile(x, 0.999), 4096)
+    yd = torch.from_numpy(y).cuda()
+    got32 = ctxs[kp.KDE_FP32_KAHAN].eval(xd, yd, h).cpu().numpy()
+    got64 = ctxs[kp.KDE_FP64_PLAIN].eval(xd, yd, h).cpu().numpy()
+    idx = np.unique(np.concatenate([[0, 1, 255, 256, 4095], np.random.default_rng(5).integers(0, 4096, 11)]))
+    ref = oracle.kde_eval(x, h, y[idx])
+    assert np.max(np.abs(got64[idx] - ref) / ref) <= 2 * x.size * U
+    assert np.max(np.abs(got32[idx] - ref) / ref) <= FP32_TOL
+
+
+def test_errors_and_empty(kp, ctxs):
+    c = ctxs[kp.KDE_FP32_KAHAN]
+    x = synth.normal(100, 1)
+    assert c.eval(x, np.zeros(0), 0.5).size == 0
+    with pytest.raises(kp.KdeError) as e:
+        c.eval(x, np.zeros(3), 0.0)
+    assert e.value.code == kp.KDE_EINVAL
+    with pytest.raises(kp.KdeError) as e:
+        c.eval(x, np.zeros(3), math.nan)
+    assert e.value.code == kp.KDE_EINVAL
+    with pytest.raises(kp.KdeError) as e:
+        c.eval(np.zeros(0), np.zeros(3), 0.5)
+    assert e.value.code == kp.KDE_EINVAL
+    bad = x.copy()
+    bad[17] = math.inf
+    with pytest.raises(kp.KdeError) as e:
+        c.eval(bad, np.zeros(3), 0.5)
+    assert e.value.code == kp.KDE_ENONFINITE
+    with pytest.raises(kp.KdeError) as e:
+        c.eval(x, np.array([0.0, math.nan]), 0.5)
+    assert e.value.code == kp.KDE_ENONFINITE
+    # the literal call: default FP64 context, host arrays
+    y = np.linspace(-2, 2, 9)
+    np.testing.assert_allclose(kp.kde_eval(x, y, 0.4), oracle.kde_eval(x, 0.4, y), rtol=1e-13)
