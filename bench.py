@@ -17,7 +17,7 @@ roofline   = the persistent kernel's algorithmic FP32 FLOP rate (10 FLOP per
 cpu_baseline = the FP64 oracle (plain C + OpenMP, all host cores) on the same
              sample, one full selection
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp32x|fp64]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp32x|fp32poly|q32|fp64]
 """
 from __future__ import annotations
 
@@ -96,7 +96,8 @@ def bench_batch(args):
     import torch
     from paper_1505_02100_amd import kdeplugin as kp
     from paper_1505_02100_amd import synth
-    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp64": kp.KDE_FP64_PLAIN}
+    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
+            "q32": kp.KDE_Q32_32, "fp64": kp.KDE_FP64_PLAIN}
     xs, names = synth.workload_batch(512, 3)
     xds = [torch.from_numpy(x).cuda() for x in xs]
     pairs = sum(x.size * (x.size - 1) for x in xs)
@@ -175,7 +176,8 @@ def bench_eval(args):
     import torch
     from paper_1505_02100_amd import kdeplugin as kp
     from paper_1505_02100_amd import synth
-    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp64": kp.KDE_FP64_PLAIN}
+    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
+            "q32": kp.KDE_Q32_32, "fp64": kp.KDE_FP64_PLAIN}
     x = synth.workload_single_lognormal(1 << 20, 2)
     n, m = x.size, 4096
     xd = torch.from_numpy(x).cuda()
@@ -237,7 +239,8 @@ def bench_serve(args):
     from paper_1505_02100_amd import kdeplugin as kp
     from paper_1505_02100_amd import synth
     from paper_1505_02100_amd.server import serve_trace
-    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp64": kp.KDE_FP64_PLAIN}
+    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
+            "q32": kp.KDE_Q32_32, "fp64": kp.KDE_FP64_PLAIN}
     trace = synth.serving_trace(rate=args.rate, duration=args.duration, master=4)
     # items of about 2^24 pairs for every request size: a step of 2^36 pairs then
     # holds thousands of items from many requests
@@ -289,7 +292,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", choices=["fp32", "fp32x", "fp64"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "fp32x", "fp32poly", "q32", "fp64"], default="fp32")
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch512", "serve", "eval4096"],
                     default="bimodal65536")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
@@ -328,8 +331,8 @@ def main():
 
     from paper_1505_02100_amd import kdeplugin as kp
 
-    prec_code = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT,
-                 "fp64": kp.KDE_FP64_PLAIN}[args.precision]
+    prec_code = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
+                 "q32": kp.KDE_Q32_32, "fp64": kp.KDE_FP64_PLAIN}[args.precision]
     w = WORKLOADS[args.workload]
     x = make_sample(w)
     n = x.size
@@ -368,7 +371,7 @@ def main():
            "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+           "dtype": {"fp64": "f64", "q32": "q32.32"}.get(args.precision, "f32"), "data": "synthetic",
            "config": {"workload": w["desc"] + ", Steps I-VII per step, samples resident in HBM",
                       "n": n, "precision": args.precision, "pairs_per_selection": pairs,
                       "tile": cfg},

@@ -80,6 +80,16 @@ extern "C" {
                             1.3e-8) in the exponent                                       */
 #define KDE_FP32_KAHAN_EXACT 2 /* as KDE_FP32_KAHAN with log2(e)/2 carried as two FP32
                                   terms (one more VALU op per pair)                    */
+#define KDE_FP32_POLYEXP 3 /* as KDE_FP32_KAHAN with 2^t evaluated by a degree-6 minimax
+                              polynomial (Remez exchange, FP32 coefficients, relative
+                              error 1.6e-8) on the FMA pipes instead of the
+                              transcendental unit, after t = n + f, n = round(t)      */
+#define KDE_Q32_32 4 /* the FPGA design's arithmetic (Section 4.2), emulated: z-scored
+                        samples and the pair-stage quantities in Q32.32 fixed point
+                        (truncating products, exact sums), the Gaussian factor from a
+                        degree-7 minimax polynomial in Q32.32; moments, cross-item sums
+                        and Steps I-III, V, VII in FP64.  Integer VALU work: slow, for
+                        studying the fixed-point design's accuracy                    */
 
 #define KDE_MEM_HOST 0
 #define KDE_MEM_DEVICE 1

@@ -73,6 +73,7 @@
 
 #include <type_traits>
 
+#include "kde_exp2_poly.h"
 #include "kde_internal.h"
 
 namespace kde {
@@ -226,7 +227,21 @@ constexpr float kYClamp = 1.0e12f;
 // Terms an FP32 accumulator takes before it is added into the FP64 lane sum.
 constexpr int kFold = 4;
 
-template <int RO, bool SAFE, bool EXACT_K>
+// 2^t from the minimax polynomial of degree kExp2PolyDegree (Remez exchange,
+// FP32 coefficients) on the FMA pipes instead of the transcendental unit:
+// t = n + f with n = round(t), f in [-1/2, 1/2], 2^t = 2^n p(f).  Arguments
+// below -200 give 0, as 2^t is below FP32's range there.
+__device__ __forceinline__ float exp2_poly(float t) {
+    t = fmaxf(t, -200.0f);
+    const float n = __builtin_rintf(t);
+    const float f = t - n;
+    float p = kExp2Poly[kExp2PolyDegree];
+#pragma unroll
+    for (int k = kExp2PolyDegree - 1; k >= 0; --k) p = fmaf(p, f, kExp2Poly[k]);
+    return __builtin_ldexpf(p, (int)n);
+}
+
+template <int RO, bool SAFE, bool EXACT_K, bool PEXP = false>
 __device__ __forceinline__ float pair_poly_exp(float vi, float vj, const PolyConsts& pc, float* e_out) {
     const float d = vi - vj;
     float p;
@@ -238,7 +253,7 @@ __device__ __forceinline__ float pair_poly_exp(float vi, float vj, const PolyCon
         // Psi4's weak dependence on g2 (about 1e-8 in h).
         float Z = fmaf(d, d, -5.0f);
         if (SAFE) Z = fminf(Z, kYClamp);
-        *e_out = __builtin_amdgcn_exp2f(-(Z * pc.k_hi));
+        *e_out = PEXP ? exp2_poly(-(Z * pc.k_hi)) : __builtin_amdgcn_exp2f(-(Z * pc.k_hi));
         const float q = fmaf(Z, Z, -30.0f);
         p = fmaf(q, Z, -40.0f);
         return p;
@@ -246,7 +261,7 @@ __device__ __forceinline__ float pair_poly_exp(float vi, float vj, const PolyCon
     float Y = d * d;
     if (SAFE) Y = fminf(Y, kYClamp);
     const float a = EXACT_K ? fmaf(Y, pc.k_hi, Y * pc.k_lo) : Y * pc.k_hi;
-    *e_out = __builtin_amdgcn_exp2f(-a);
+    *e_out = PEXP ? exp2_poly(-a) : __builtin_amdgcn_exp2f(-a);
     if (RO == 6) {
         float q = Y - 15.0f;
         q = fmaf(q, Y, 45.0f);
@@ -258,29 +273,29 @@ __device__ __forceinline__ float pair_poly_exp(float vi, float vj, const PolyCon
     return p;
 }
 
-template <int RO, bool SAFE, bool EXACT_K>
+template <int RO, bool SAFE, bool EXACT_K, bool PEXP = false>
 __device__ __forceinline__ float pair_term_f32(float vi, float vj, const PolyConsts& pc) {
     float e;
-    const float p = pair_poly_exp<RO, SAFE, EXACT_K>(vi, vj, pc, &e);
+    const float p = pair_poly_exp<RO, SAFE, EXACT_K, PEXP>(vi, vj, pc, &e);
     return p * e;
 }
 
-template <int RO, bool SAFE, bool EXACT_K>
+template <int RO, bool SAFE, bool EXACT_K, bool PEXP = false>
 __device__ __forceinline__ void pair_acc_f32(float vi, float vj, float& acc, const PolyConsts& pc) {
     float e;
-    const float p = pair_poly_exp<RO, SAFE, EXACT_K>(vi, vj, pc, &e);
+    const float p = pair_poly_exp<RO, SAFE, EXACT_K, PEXP>(vi, vj, pc, &e);
     acc = fmaf(p, e, acc);
 }
 
-template <int RO, bool SAFE, bool EXACT_K, int R>
+template <int RO, bool SAFE, bool EXACT_K, int R, bool PEXP = false>
 __device__ __forceinline__ void pair_b128_f32(const float (&ui)[R], float4 v, float (&acc)[R][4],
                                               const PolyConsts& pc) {
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], v.x, acc[k][0], pc);
-        pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], v.y, acc[k][1], pc);
-        pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], v.z, acc[k][2], pc);
-        pair_acc_f32<RO, SAFE, EXACT_K>(ui[k], v.w, acc[k][3], pc);
+        pair_acc_f32<RO, SAFE, EXACT_K, PEXP>(ui[k], v.x, acc[k][0], pc);
+        pair_acc_f32<RO, SAFE, EXACT_K, PEXP>(ui[k], v.y, acc[k][1], pc);
+        pair_acc_f32<RO, SAFE, EXACT_K, PEXP>(ui[k], v.z, acc[k][2], pc);
+        pair_acc_f32<RO, SAFE, EXACT_K, PEXP>(ui[k], v.w, acc[k][3], pc);
     }
 }
 
@@ -331,7 +346,7 @@ __device__ __forceinline__ void store_cols(T* tile, const double (&v)[TJ / BLOCK
     }
 }
 
-template <int RO, bool SAFE, bool EXACT_K, int R, int BLOCK>
+template <int RO, bool SAFE, bool EXACT_K, int R, int BLOCK, bool PEXP = false>
 __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double mean, double scale,
                                 const PolyConsts& pc, float* tile, double* red) {
     constexpr int TI = BLOCK * R;
@@ -376,7 +391,7 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
             const float uj = tile[j - cj];
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const float t = pair_term_f32<RO, SAFE, EXACT_K>(ui[k], uj, pc);
+                const float t = pair_term_f32<RO, SAFE, EXACT_K, PEXP>(ui[k], uj, pc);
                 const bool live = j > wlo + lane + (int64_t)WAVE * k;
                 tot[k] += live ? (double)t : 0.0;
             }
@@ -388,15 +403,15 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
             const float4* t4 = reinterpret_cast<const float4*>(tile);
             for (; jj + 4 * kFold <= len; jj += 4 * kFold) {
 #pragma unroll
-                for (int q = 0; q < kFold; ++q) pair_b128_f32<RO, SAFE, EXACT_K, R>(ui, t4[(jj >> 2) + q], acc, pc);
+                for (int q = 0; q < kFold; ++q) pair_b128_f32<RO, SAFE, EXACT_K, R, PEXP>(ui, t4[(jj >> 2) + q], acc, pc);
                 fold_f64<R>(acc, tot);
             }
-            for (; jj + 4 <= len; jj += 4) pair_b128_f32<RO, SAFE, EXACT_K, R>(ui, t4[jj >> 2], acc, pc);
+            for (; jj + 4 <= len; jj += 4) pair_b128_f32<RO, SAFE, EXACT_K, R, PEXP>(ui, t4[jj >> 2], acc, pc);
             fold_f64<R>(acc, tot);
             for (; jj < len; ++jj) {
                 const float uj = tile[jj];
 #pragma unroll
-                for (int k = 0; k < R; ++k) tot[k] += (double)pair_term_f32<RO, SAFE, EXACT_K>(ui[k], uj, pc);
+                for (int k = 0; k < R; ++k) tot[k] += (double)pair_term_f32<RO, SAFE, EXACT_K, PEXP>(ui[k], uj, pc);
             }
         }
     }
@@ -484,6 +499,113 @@ __device__ double pair_item_f64(const View& d, int32_t rb, int32_t cb, double me
     return block_sum<BLOCK>(lane_tot, red);
 }
 
+// ---------------------------------------------- Q32.32 fixed point (emulation)
+// The arithmetic of the paper's FPGA design (Section 4.2): z-scored samples
+// and every pair-stage quantity in Q32.32, value = i / 2^32 in a signed 64-bit
+// integer (sign, 31 integer and 32 fraction bits); products truncate (floor),
+// sums are exact; the Gaussian factor comes from a minimax polynomial (Remez
+// exchange) after range reduction.  Terms with |u| >= 16 are 0: their
+// Gaussian factor is below 2^-128, far below Q32.32's resolution, and the
+// polynomial would leave Q32.32's range.  Lane sums stay in Q32.32 (at most
+// 15 times the lane's pairs, far inside 2^31); block sums are exact 64-bit
+// integer sums, and the stage sum is the exact fixed-point accumulator.
+using q32 = int64_t;
+constexpr q32 kQOne = (q32)1 << 32;
+
+__device__ __forceinline__ q32 q_mul(q32 a, q32 b) { return (q32)(((__int128)a * (__int128)b) >> 32); }
+
+__device__ __forceinline__ q32 q_from(double v) { return (q32)floor(v * 4294967296.0); }
+
+// 2^-a for a >= 0: a = n + f with n = round(a), 2^-a = 2^-n p(-f), -f in [-1/2, 1/2]
+__device__ __forceinline__ q32 q_exp2_neg(q32 a) {
+    const q32 n = (a + (kQOne >> 1)) >> 32;
+    const q32 x = n * kQOne - a;
+    q32 p = kExp2PolyQ[kExp2PolyQDegree];
+#pragma unroll
+    for (int k = kExp2PolyQDegree - 1; k >= 0; --k) p = q_mul(p, x) + kExp2PolyQ[k];
+    return n >= 62 ? 0 : (p >> n);
+}
+
+template <int RO>
+__device__ __forceinline__ q32 q_term(q32 zi, q32 zj, q32 ginv) {
+    const q32 u = q_mul(zi - zj, ginv);
+    if (u >= 16 * kQOne || u <= -16 * kQOne) return 0;
+    const q32 t = q_mul(u, u);
+    q32 p;
+    if (RO == 6)
+        p = q_mul(q_mul(t - 15 * kQOne, t) + 45 * kQOne, t) - 15 * kQOne;
+    else
+        p = q_mul(t - 6 * kQOne, t) + 3 * kQOne;
+    // exp(-t/2) = 2^(-(t/2) log2(e))
+    return q_mul(p, q_exp2_neg(q_mul(t >> 1, 2 * kQLog2eHalf)));
+}
+
+template <int BLOCK>
+__device__ __forceinline__ q32 block_sum_q(q32 v, q32* red) {
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    q32 tot = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < BLOCK / WAVE; ++w) tot += red[w];
+    }
+    __syncthreads();
+    return tot;  // valid in thread 0
+}
+
+// One pair item in Q32.32; returns the item's exact sum (thread 0).
+template <int RO, int R, int BLOCK>
+__device__ q32 pair_item_q32(const View& d, int32_t rb, int32_t cb, double mean, double scale, double sigma,
+                             q32* tile, q32* red) {
+    constexpr int TI = BLOCK * R;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int64_t n = d.n;
+    const int64_t r0 = (int64_t)rb * TI;
+    const int64_t wlo = r0 + (int64_t)wave * WAVE * R;
+    const int64_t whi = wlo + WAVE * R;
+    // z-scores (the reciprocal of sigma, not a division) and the reciprocal bandwidth in z units
+    const double inv_sigma = 1.0 / sigma;
+    const q32 ginv = q_from(sigma * scale);
+
+    q32 zi[R], acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int64_t i = wlo + lane + (int64_t)WAVE * k;
+        zi[k] = i < n ? q_from((load_x(d.x, d.dtype, i) - mean) * inv_sigma) : 0;
+        acc[k] = 0;
+    }
+    int64_t c0, c1;
+    item_columns(n, r0, d.W, cb, &c0, &c1);
+    for (int64_t cj = c0; cj < c1; cj += TJ) {
+        const int len = (int)min((int64_t)TJ, c1 - cj);
+        __syncthreads();
+        for (int e = tid; e < len; e += BLOCK) tile[e] = q_from((load_x(d.x, d.dtype, cj + e) - mean) * inv_sigma);
+        __syncthreads();
+        const int64_t ma = max(cj, wlo + 1), mb = min(cj + (int64_t)len, whi);
+        for (int64_t j = ma; j < mb; ++j) {
+            const q32 zj = tile[j - cj];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const q32 t = q_term<RO>(zi[k], zj, ginv);
+                acc[k] += j > wlo + lane + (int64_t)WAVE * k ? t : 0;
+            }
+        }
+        for (int64_t j = max(cj, whi); j < cj + len; ++j) {
+            const q32 zj = tile[j - cj];
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += q_term<RO>(zi[k], zj, ginv);
+        }
+    }
+    q32 lane_tot = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) lane_tot += acc[k];
+    return block_sum_q<BLOCK>(lane_tot, red);
+}
+
 // ------------------------------------------------------------ finalisers
 // Scalar formulas of Algorithm 1 in FP64, written in scale-free form so that
 // samples with very large or small spread do not overflow sigma^9 or g^7:
@@ -553,7 +675,7 @@ __device__ Published finalize_stage(const View& d, State* st, int32_t stage, dou
     }
     case ST_PSI6: {
         // the default FP32 path evaluates Step IV with exp2(-k Z), Z = Y - 5
-        const double S6 = (PREC == 1 ? exp2(-5.0 * (double)pc.k_hi) : 1.0) * tot / rt2pi;
+        const double S6 = (PREC == 1 || PREC == 3 ? exp2(-5.0 * (double)pc.k_hi) : 1.0) * tot / rt2pi;
         st_f64(&st->S6, S6);
         const double A6 = 2.0 * S6 + nd * K6_0;
         const double g1 = d.mode == MODE_PLUGIN ? pr.g1 : d.psi_g;
@@ -637,6 +759,16 @@ __device__ __forceinline__ void fx_add(int64_t (&acc)[4], double v) {
         lo = ~lo + 1ull;
         hi = ~hi + (lo == 0ull ? 1ull : 0ull);
     }
+    acc[0] += (int64_t)(lo & 0xffffffffull);
+    acc[1] += (int64_t)(lo >> 32);
+    acc[2] += (int64_t)(hi & 0xffffffffull);
+    acc[3] += (int64_t)(int32_t)(uint32_t)(hi >> 32);
+}
+
+// Exact accumulation of a Q32.32 partial v (value v / 2^32): V = v 2^32.
+__device__ __forceinline__ void fx_add_q(int64_t (&acc)[4], int64_t v) {
+    const __int128 V = (__int128)v << 32;
+    const uint64_t lo = (uint64_t)V, hi = (uint64_t)(V >> 64);
     acc[0] += (int64_t)(lo & 0xffffffffull);
     acc[1] += (int64_t)(lo >> 32);
     acc[2] += (int64_t)(hi & 0xffffffffull);
@@ -755,7 +887,7 @@ __device__ void complete_items(const LaunchArgs& A, int32_t ds, const View& d, S
 // every flag is published.
 template <int PREC, int R, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
-    using TileT = typename std::conditional<PREC >= 1, float, double>::type;
+    using TileT = typename std::conditional<PREC >= 1 && PREC <= 3, float, double>::type;
     __shared__ __align__(16) TileT tile[TJ];
     __shared__ double red[BLOCK / WAVE];
     __shared__ uint32_t sh_ticket;
@@ -841,6 +973,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         const int32_t safe = sh_safe;
 
         double v = 0.0, aux = 0.0;
+        q32 vq = 0;  // Q32.32 item sum (fixed-point mode)
         if (status == 0) {
             switch (it.stage) {
             case ST_SUM:
@@ -851,15 +984,23 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
                 break;
             case ST_PSI6:
             case ST_PSI4:
-                if constexpr (PREC >= 1) {
+                if constexpr (PREC == 4) {
+                    // sigma was written by Step I's finaliser before the flag this item waited for
+                    const double sigma = ld_f64(&st->sigma);
+                    q32* tl = reinterpret_cast<q32*>(tile);
+                    q32* rq = reinterpret_cast<q32*>(red);
+                    vq = it.stage == ST_PSI6 ? pair_item_q32<6, R, BLOCK>(d, it.a, it.b, mean, scale, sigma, tl, rq)
+                                             : pair_item_q32<4, R, BLOCK>(d, it.a, it.b, mean, scale, sigma, tl, rq);
+                } else if constexpr (PREC >= 1) {
                     constexpr bool XK = PREC == 2;
+                    constexpr bool PX = PREC == 3;
                     float* tl = reinterpret_cast<float*>(tile);
                     if (it.stage == ST_PSI6)
-                        v = safe ? pair_item_f32<6, true, XK, R, BLOCK>(d, it.a, it.b, mean, scale, A.pc, tl, red)
-                                 : pair_item_f32<6, false, XK, R, BLOCK>(d, it.a, it.b, mean, scale, A.pc, tl, red);
+                        v = safe ? pair_item_f32<6, true, XK, R, BLOCK, PX>(d, it.a, it.b, mean, scale, A.pc, tl, red)
+                                 : pair_item_f32<6, false, XK, R, BLOCK, PX>(d, it.a, it.b, mean, scale, A.pc, tl, red);
                     else
-                        v = safe ? pair_item_f32<4, true, XK, R, BLOCK>(d, it.a, it.b, mean, scale, A.pc, tl, red)
-                                 : pair_item_f32<4, false, XK, R, BLOCK>(d, it.a, it.b, mean, scale, A.pc, tl, red);
+                        v = safe ? pair_item_f32<4, true, XK, R, BLOCK, PX>(d, it.a, it.b, mean, scale, A.pc, tl, red)
+                                 : pair_item_f32<4, false, XK, R, BLOCK, PX>(d, it.a, it.b, mean, scale, A.pc, tl, red);
                 } else {
                     double* tl = reinterpret_cast<double*>(tile);
                     if (it.stage == ST_PSI6)
@@ -874,7 +1015,9 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         }
 
         if (tid == 0) {
-            if (it.stage >= ST_PSI6) {
+            if (PREC == 4 && it.stage >= ST_PSI6) {
+                fx_add_q(pacc, vq);
+            } else if (it.stage >= ST_PSI6) {
                 if (fabs(v) < kFxLimit)
                     fx_add(pacc, v);
                 else if (status == 0)
@@ -929,6 +1072,12 @@ hipError_t launch_persistent(int prec, int R, int grid, hipStream_t s, const Lau
     case 2 * 8 + 1: return launch_one<2, 1>(grid, s, a);
     case 2 * 8 + 2: return launch_one<2, 2>(grid, s, a);
     case 2 * 8 + 4: return launch_one<2, 4>(grid, s, a);
+    case 3 * 8 + 1: return launch_one<3, 1>(grid, s, a);
+    case 3 * 8 + 2: return launch_one<3, 2>(grid, s, a);
+    case 3 * 8 + 4: return launch_one<3, 4>(grid, s, a);
+    case 4 * 8 + 1: return launch_one<4, 1>(grid, s, a);
+    case 4 * 8 + 2: return launch_one<4, 2>(grid, s, a);
+    case 4 * 8 + 4: return launch_one<4, 4>(grid, s, a);
     default: return hipErrorInvalidValue;
     }
 }
@@ -944,6 +1093,12 @@ hipError_t persistent_occupancy(int prec, int R, int* blocks_per_cu) {
     case 2 * 8 + 1: return occ_one<2, 1>(blocks_per_cu);
     case 2 * 8 + 2: return occ_one<2, 2>(blocks_per_cu);
     case 2 * 8 + 4: return occ_one<2, 4>(blocks_per_cu);
+    case 3 * 8 + 1: return occ_one<3, 1>(blocks_per_cu);
+    case 3 * 8 + 2: return occ_one<3, 2>(blocks_per_cu);
+    case 3 * 8 + 4: return occ_one<3, 4>(blocks_per_cu);
+    case 4 * 8 + 1: return occ_one<4, 1>(blocks_per_cu);
+    case 4 * 8 + 2: return occ_one<4, 2>(blocks_per_cu);
+    case 4 * 8 + 4: return occ_one<4, 4>(blocks_per_cu);
     default: return hipErrorInvalidValue;
     }
 }

@@ -566,7 +566,7 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     kde_options_init(&o);
     if (opt) o = *opt;
     if (o.precision != KDE_FP64_PLAIN && o.precision != KDE_FP32_KAHAN &&
-        o.precision != KDE_FP32_KAHAN_EXACT)
+        o.precision != KDE_FP32_KAHAN_EXACT && o.precision != KDE_FP32_POLYEXP && o.precision != KDE_Q32_32)
         return set_err(KDE_EINVAL, "bad precision");
     if (o.rows_per_lane != 0 && o.rows_per_lane != 1 && o.rows_per_lane != 2 && o.rows_per_lane != 4)
         return set_err(KDE_EINVAL, "rows_per_lane must be 0, 1, 2 or 4");

@@ -55,6 +55,8 @@ KDE_EBUSY = -7
 KDE_FP64_PLAIN = 0
 KDE_FP32_KAHAN = 1
 KDE_FP32_KAHAN_EXACT = 2
+KDE_FP32_POLYEXP = 3
+KDE_Q32_32 = 4
 KDE_MEM_HOST = 0
 KDE_MEM_DEVICE = 1
 KDE_F64 = 0

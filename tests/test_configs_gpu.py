@@ -32,7 +32,8 @@ def kp():
 
 @pytest.fixture(scope="module")
 def ctxs(kp):
-    c = {p: kp.Context(p) for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT)}
+    c = {p: kp.Context(p) for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT,
+                                    kp.KDE_FP32_POLYEXP)}
     yield c
     for v in c.values():
         v.close()
@@ -49,7 +50,7 @@ def test_bimodal_65536_full_oracle(kp, ctxs):
     xd = torch.from_numpy(x).cuda()
     r64 = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth(xd)
     assert _rel(r64.h, ref.h) < 1e-12 and _rel(r64.psi6, ref.psi6) < 1e-12 and _rel(r64.psi4, ref.psi4) < 1e-12
-    for p in (kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT):
+    for p in (kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT, kp.KDE_FP32_POLYEXP):
         r = ctxs[p].plugin_bandwidth(xd)
         assert _rel(r.h, ref.h) < 1e-6, (p, r.h, ref.h)
         assert _rel(r.psi6, ref.psi6) < 1e-5 and _rel(r.psi4, ref.psi4) < 5e-6
@@ -100,7 +101,7 @@ def test_lognormal_1m_sampled_items_and_properties(kp, ctxs):
     # scale and shift equivariance h(aX + b) = |a| h(X), and FP32 against FP64
     hb = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth(torch.from_numpy(base).cuda()).h
     assert _rel(r64.h, 1e3 * hb) < 1e-10
-    for p in (kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT):
+    for p in (kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT, kp.KDE_FP32_POLYEXP):
         r = ctxs[p].plugin_bandwidth(xd)
         assert _rel(r.h, r64.h) < 1e-6, (p, r.h, r64.h)
 

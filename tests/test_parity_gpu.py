@@ -52,6 +52,20 @@ def ctx32x(kp):
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx32p(kp):
+    c = kp.Context(kp.KDE_FP32_POLYEXP)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctxq(kp):
+    c = kp.Context(kp.KDE_Q32_32)
+    yield c
+    c.close()
+
+
 def _rel(a, b):
     return abs(a - b) / abs(b)
 
@@ -97,6 +111,99 @@ def test_plugin_many_tiles(ctx64, ctx32, n):
     ref = oracle.plugin(x)
     _check(ctx64.plugin_bandwidth(x), ref, TOL64, TOL64)
     _check(ctx32.plugin_bandwidth(x), ref, TOL32_H, TOL32_PSI)
+
+
+@pytest.mark.parametrize("n", [2, 65, 1000, 4097, 33333])
+def test_plugin_fp32_polynomial_exp2(ctx32p, n):
+    # the Gaussian factor from the Remez polynomial instead of v_exp_f32:
+    # the same FP32 tolerances against the oracle, deterministic
+    x = synth.draw(["normal", "bimodal", "t3"][n % 3], n, 70 + n)
+    ref = oracle.plugin(x)
+    a = ctx32p.plugin_bandwidth(x)
+    _check(a, ref, TOL32_H, TOL32_PSI)
+    b = ctx32p.plugin_bandwidth(x)
+    assert (a.h, a.psi6, a.psi4) == (b.h, b.psi6, b.psi4)
+    for r, g in ((4, 0.4), (6, 0.05)):
+        assert _rel(ctx32p.psi(x, r, g), oracle.psi(x, r, g)) < TOL32_PSI
+
+
+def _q32_psi_bound(x, r, g):
+    """Bound on the Psi_r(g) error of the Q32.32 mode, from its arithmetic.
+
+    In units of one Q32.32 step (2^-32), per pair with |u| < 16: the
+    z-scores truncate (|dd| <= 2), u = d (sigma/g) truncates (|du| <=
+    2 ginv + 1 + |d|), t = u^2 (|dt| <= 2|u| du + 1), the exponent
+    a = (t/2) log2(e) (|da| <= 0.73 dt + 2 + a/2).  The Gaussian factor is a
+    Horner polynomial (at most 12 steps of error) shifted right by
+    n = round(a) with a truncation: |de| <= min(1, e 2^32) + 12 2^-n, plus
+    e ln2 da from its argument.  The Hermite factor carries |p'(t)| dt and
+    its own truncations (1 + t), the product one more step:
+        |dterm| <= |p| (min(1, e 2^32) + 12 2^-n + e ln2 da) + e (|p'| dt + 1 + t) + 1.
+    The pair sum S enters Psi as 2 S / (sqrt(2 pi) n^2 g^(r+1)).  The first
+    part dominates at small g: the Gaussian factor has an absolute, not a
+    relative, resolution, so tail terms (t of 30 to 50, where e is a few
+    steps) lose their accuracy, multiplied by |p| ~ t^3.  This is the
+    fixed-point design's accuracy limit, which the mode is there to show.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    n = x.size
+    sig = x.std(ddof=1)
+    z = (x - x.mean()) / sig
+    ginv = sig / g
+    q = 2.0 ** 32
+    tot = 0.0
+    for i in range(n - 1):
+        u = (z[i] - z[i + 1:]) * ginv
+        u = u[np.abs(u) < 16]
+        d = u / ginv
+        t = u * u
+        e = np.exp(-t / 2)
+        a = 0.7213475204444817 * t
+        if r == 6:
+            pv = ((t - 15) * t + 45) * t - 15
+            dp = (3 * t - 30) * t + 45
+        else:
+            pv = (t - 6) * t + 3
+            dp = 2 * t - 6
+        du = 2 * ginv + 1 + np.abs(d)
+        dt = 2 * np.abs(u) * du + 1
+        da = 0.73 * dt + 2 + a / 2
+        de = np.minimum(1.0, e * q) + 12.0 * np.exp2(-np.round(a)) + e * math.log(2) * da
+        tot += np.sum(np.abs(pv) * de + e * (np.abs(dp) * dt + 1 + t) + 1)
+    return 2 * tot / q / math.sqrt(2 * math.pi) / (n * n * g ** (r + 1))
+
+
+@pytest.mark.parametrize("n", [2, 65, 1000, 4097])
+def test_plugin_q32_fixed_point(ctxq, n):
+    # the FPGA design's Q32.32 arithmetic against the oracle, within the
+    # bounds its arithmetic gives (_q32_psi_bound): Psi6 at g1, Psi4 at g2 (plus
+    # the effect of g2's own small error), h = (R(K)/(n Psi4))^(1/5) through
+    # Psi4 alone; Psi at fixed g likewise.  The sums are integers added
+    # exactly, so the result repeats bitwise.
+    x = synth.draw(["normal", "bimodal", "t3"][n % 3], n, 90 + n)
+    ref = oracle.plugin(x)
+    a = ctxq.plugin_bandwidth(x)
+    assert a.status == 0
+    b6 = _q32_psi_bound(x, 6, ref.g1) + 1e-12 * abs(ref.psi6)
+    assert abs(a.psi6 - ref.psi6) <= b6
+    dg2 = _rel(a.g2, ref.g2)
+    rel4 = (_q32_psi_bound(x, 4, ref.g2) + 1e-12 * ref.psi4) / ref.psi4 + 10 * dg2
+    assert _rel(a.psi4, ref.psi4) <= rel4
+    assert _rel(a.h, ref.h) <= 0.2 * rel4 + 1e-12
+    b = ctxq.plugin_bandwidth(x)
+    assert (a.h, a.psi6, a.psi4) == (b.h, b.psi6, b.psi4)
+    for r, g in ((4, 0.4), (6, 0.05)):
+        want = oracle.psi(x, r, g)
+        bound = _q32_psi_bound(x, r, g) + 1e-12 * abs(want)
+        assert abs(ctxq.psi(x, r, g) - want) <= bound, (r, g, bound / abs(want))
+
+
+def test_q32_sums_do_not_depend_on_the_decomposition(kp, ctxq):
+    # integer sums: any split of the work into items gives the same Psi bitwise
+    x = synth.bimodal(9000, 4)
+    a = ctxq.psi(x, 6, 0.3)
+    with kp.Context(kp.KDE_Q32_32, target_items=97) as other:
+        assert other.psi(x, 6, 0.3) == a
 
 
 @pytest.mark.parametrize("r", [4, 6])
