@@ -99,11 +99,11 @@ int64_t target_items_for(const kde_ctx* c, int64_t n) {
     while (lg < 62 && ((int64_t)2 << lg) <= n) ++lg;
     for (int b = lg; b >= 0; --b)
         if (c->bucket_target[b] > 0) return c->bucket_target[b];
-    // about 2^18 pairs per item (W = 1024 columns of a 256-row tile), at
-    // least 1024 items so small samples still spread over the device, at
-    // most 32768 so the work list and slots stay small
-    const double P = 0.5 * (double)n * (double)(n - 1);
-    return std::min<int64_t>(32768, std::max<int64_t>(1024, (int64_t)std::ceil(P / 262144.0)));
+    // about n/10 items per stage, i.e. chunks of about n/51 columns (rounded
+    // up to a power of two) for 256-row tiles; at least 1024 items so small
+    // samples still spread over the device, at most 65536 so the work list
+    // stays small (beyond n = 2^18 the count hardly matters)
+    return std::min<int64_t>(65536, std::max<int64_t>(1024, (n + 9) / 10));
 }
 
 // Tune table (written by kde_autotune): a small JSON object
