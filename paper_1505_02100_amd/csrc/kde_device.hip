@@ -308,6 +308,186 @@ __device__ __forceinline__ void fold_f64(float (&acc)[R][4], double (&tot)[R]) {
     }
 }
 
+// Step VI at R = 1 without the clamp (the default FP32 path): 16 columns
+// (four LDS b128 reads) against one row per lane, written out as a fixed
+// instruction sequence.  The operations are exactly those of pair_acc_f32 and
+// fold_f64 (per pair d = ui - xj, Y = d d, q = fma(d, d, -6), p = fma(q, Y, 3),
+// e = 2^(Y (-k)); column c of every read goes to accumulator c in read order;
+// then (a0 + a1) + (a2 + a3) into the FP64 lane total), so the result is
+// bitwise that of the loop it replaces.  Only the order differs: the
+// compiler's schedule of this step ran at 5.3e12 pairs/s on MI355X against
+// 6.0e12 for Step IV's, and timing valid orders of the step's dependency graph
+// found this one at 6.1e12 (Step IV's own compiled order was already as fast
+// as any tried).  Registers are the compiler's (every value is an operand);
+// an s_nop separates a v_exp_f32 from a VALU op that reads its result in the
+// next instruction (gfx950 needs one wait state there).
+__device__ __forceinline__ void pair16_r4_f32(const float4* t4, float ui, float k, double& tot) {
+    float x[16], s[16];
+    double t64;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float4 v = t4[b];
+        x[4 * b] = v.x;
+        x[4 * b + 1] = v.y;
+        x[4 * b + 2] = v.z;
+        x[4 * b + 3] = v.w;
+    }
+    asm volatile(
+        "v_sub_f32_e32 %[x6], %[ui], %[x6]\n"
+        "v_sub_f32_e32 %[x10], %[ui], %[x10]\n"
+        "v_sub_f32_e32 %[x12], %[ui], %[x12]\n"
+        "v_sub_f32_e32 %[x1], %[ui], %[x1]\n"
+        "v_fmaak_f32 %[s0], %[x12], %[x12], 0xc0c00000\n"
+        "v_sub_f32_e32 %[x5], %[ui], %[x5]\n"
+        "v_sub_f32_e32 %[x15], %[ui], %[x15]\n"
+        "v_fmaak_f32 %[s1], %[x5], %[x5], 0xc0c00000\n"
+        "v_sub_f32_e32 %[x7], %[ui], %[x7]\n"
+        "v_sub_f32_e32 %[x11], %[ui], %[x11]\n"
+        "v_mul_f32_e32 %[x5], %[x5], %[x5]\n"
+        "v_fmaak_f32 %[s2], %[x7], %[x7], 0xc0c00000\n"
+        "v_mul_f32_e32 %[s3], %[x11], %[x11]\n"
+        "v_fmaak_f32 %[s4], %[x1], %[x1], 0xc0c00000\n"
+        "v_mul_f32_e32 %[x7], %[x7], %[x7]\n"
+        "v_mul_f32_e32 %[s5], %[x6], %[x6]\n"
+        "v_fmaak_f32 %[s1], %[s1], %[x5], 0x40400000\n"
+        "v_sub_f32_e32 %[x2], %[ui], %[x2]\n"
+        "v_sub_f32_e32 %[x13], %[ui], %[x13]\n"
+        "v_mul_f32_e32 %[s6], %[x15], %[x15]\n"
+        "v_fmaak_f32 %[s7], %[x10], %[x10], 0xc0c00000\n"
+        "v_mul_f32_e64 %[x5], %[x5], -%[k]\n"
+        "v_sub_f32_e32 %[x14], %[ui], %[x14]\n"
+        "v_mul_f32_e32 %[x10], %[x10], %[x10]\n"
+        "v_fmaak_f32 %[s2], %[s2], %[x7], 0x40400000\n"
+        "v_mul_f32_e32 %[s8], %[x13], %[x13]\n"
+        "v_mul_f32_e32 %[s9], %[x14], %[x14]\n"
+        "v_fmaak_f32 %[s10], %[x2], %[x2], 0xc0c00000\n"
+        "v_mul_f32_e32 %[x1], %[x1], %[x1]\n"
+        "v_sub_f32_e32 %[x8], %[ui], %[x8]\n"
+        "v_fmaak_f32 %[s11], %[x8], %[x8], 0xc0c00000\n"
+        "v_sub_f32_e32 %[x4], %[ui], %[x4]\n"
+        "v_sub_f32_e32 %[x3], %[ui], %[x3]\n"
+        "v_mul_f32_e32 %[s12], %[x3], %[x3]\n"
+        "v_fmaak_f32 %[x11], %[x11], %[x11], 0xc0c00000\n"
+        "v_fmaak_f32 %[x14], %[x14], %[x14], 0xc0c00000\n"
+        "v_fmaak_f32 %[s7], %[s7], %[x10], 0x40400000\n"
+        "v_mul_f32_e32 %[x12], %[x12], %[x12]\n"
+        "v_fmaak_f32 %[s13], %[x4], %[x4], 0xc0c00000\n"
+        "v_fmaak_f32 %[x13], %[x13], %[x13], 0xc0c00000\n"
+        "v_mul_f32_e32 %[x4], %[x4], %[x4]\n"
+        "v_mul_f32_e32 %[x8], %[x8], %[x8]\n"
+        "v_fmaak_f32 %[x15], %[x15], %[x15], 0xc0c00000\n"
+        "v_fmaak_f32 %[s11], %[s11], %[x8], 0x40400000\n"
+        "v_fmaak_f32 %[x3], %[x3], %[x3], 0xc0c00000\n"
+        "v_sub_f32_e32 %[x9], %[ui], %[x9]\n"
+        "v_fmaak_f32 %[s4], %[s4], %[x1], 0x40400000\n"
+        "v_fmaak_f32 %[s14], %[x9], %[x9], 0xc0c00000\n"
+        "v_fmaak_f32 %[x15], %[x15], %[s6], 0x40400000\n"
+        "v_fmaak_f32 %[x11], %[x11], %[s3], 0x40400000\n"
+        "v_sub_f32_e32 %[x0], %[ui], %[x0]\n"
+        "v_fmaak_f32 %[s0], %[s0], %[x12], 0x40400000\n"
+        "v_fmaak_f32 %[x3], %[x3], %[s12], 0x40400000\n"
+        "v_fmaak_f32 %[s15], %[x0], %[x0], 0xc0c00000\n"
+        "v_fmaak_f32 %[s13], %[s13], %[x4], 0x40400000\n"
+        "v_mul_f32_e32 %[x0], %[x0], %[x0]\n"
+        "v_fmaak_f32 %[x6], %[x6], %[x6], 0xc0c00000\n"
+        "v_fmaak_f32 %[x14], %[x14], %[s9], 0x40400000\n"
+        "v_fmaak_f32 %[x6], %[x6], %[s5], 0x40400000\n"
+        "v_fmaak_f32 %[s15], %[s15], %[x0], 0x40400000\n"
+        "v_mul_f32_e32 %[x9], %[x9], %[x9]\n"
+        "v_mul_f32_e64 %[x12], %[x12], -%[k]\n"
+        "v_mul_f32_e64 %[s12], %[s12], -%[k]\n"
+        "v_mul_f32_e64 %[x0], %[x0], -%[k]\n"
+        "v_mul_f32_e64 %[s3], %[s3], -%[k]\n"
+        "v_mul_f32_e64 %[s5], %[s5], -%[k]\n"
+        "v_mul_f32_e64 %[x7], %[x7], -%[k]\n"
+        "v_mul_f32_e64 %[x1], %[x1], -%[k]\n"
+        "v_mul_f32_e64 %[x8], %[x8], -%[k]\n"
+        "v_mul_f32_e64 %[s6], %[s6], -%[k]\n"
+        "v_mul_f32_e64 %[s9], %[s9], -%[k]\n"
+        "v_mul_f32_e64 %[x10], %[x10], -%[k]\n"
+        "v_mul_f32_e64 %[x4], %[x4], -%[k]\n"
+        "v_exp_f32_e32 %[s12], %[s12]\n"
+        "v_exp_f32_e32 %[x10], %[x10]\n"
+        "v_exp_f32_e32 %[x12], %[x12]\n"
+        "v_exp_f32_e32 %[s5], %[s5]\n"
+        "v_exp_f32_e32 %[x4], %[x4]\n"
+        "v_exp_f32_e32 %[x0], %[x0]\n"
+        "v_exp_f32_e32 %[x1], %[x1]\n"
+        "v_exp_f32_e32 %[x5], %[x5]\n"
+        "v_exp_f32_e32 %[x7], %[x7]\n"
+        "v_exp_f32_e32 %[s9], %[s9]\n"
+        "v_exp_f32_e32 %[s6], %[s6]\n"
+        "v_exp_f32_e32 %[s3], %[s3]\n"
+        "v_exp_f32_e32 %[x8], %[x8]\n"
+        "v_fmaak_f32 %[x13], %[x13], %[s8], 0x40400000\n"
+        "v_fmaak_f32 %[s14], %[s14], %[x9], 0x40400000\n"
+        "v_mul_f32_e32 %[x3], %[x3], %[s12]\n"
+        "v_mul_f32_e32 %[s12], %[s4], %[x1]\n"
+        "v_mul_f32_e32 %[s4], %[x2], %[x2]\n"
+        "v_fmaak_f32 %[x1], %[s10], %[s4], 0x40400000\n"
+        "v_fmac_f32_e32 %[x3], %[s2], %[x7]\n"
+        "v_fmac_f32_e32 %[x3], %[x11], %[s3]\n"
+        "v_fmac_f32_e32 %[s12], %[s1], %[x5]\n"
+        "v_mul_f32_e32 %[x2], %[s15], %[x0]\n"
+        "v_fmac_f32_e32 %[x2], %[s13], %[x4]\n"
+        "v_fmac_f32_e32 %[x2], %[s11], %[x8]\n"
+        "v_fmac_f32_e32 %[x3], %[x15], %[s6]\n"
+        "v_fmac_f32_e32 %[x2], %[s0], %[x12]\n"
+        "v_mul_f32_e64 %[s10], %[x9], -%[k]\n"
+        "v_mul_f32_e64 %[s2], %[s4], -%[k]\n"
+        "v_mul_f32_e64 %[x7], %[s8], -%[k]\n"
+        "v_exp_f32_e32 %[x11], %[x7]\n"
+        "v_exp_f32_e32 %[s3], %[s10]\n"
+        "v_exp_f32_e32 %[s1], %[s2]\n"
+        "s_nop 0\n"
+        "v_mul_f32_e32 %[x5], %[x1], %[s1]\n"
+        "v_fmac_f32_e32 %[x5], %[x6], %[s5]\n"
+        "v_fmac_f32_e32 %[x5], %[s7], %[x10]\n"
+        "v_fmac_f32_e32 %[x5], %[x14], %[s9]\n"
+        "v_fmac_f32_e32 %[s12], %[s14], %[s3]\n"
+        "v_fmac_f32_e32 %[s12], %[x13], %[x11]\n"
+        "v_add_f32_e32 %[s15], %[x2], %[s12]\n"
+        "v_add_f32_e32 %[x0], %[x5], %[x3]\n"
+        "v_add_f32_e32 %[s13], %[s15], %[x0]\n"
+        "v_cvt_f64_f32_e32 %[t64], %[s13]\n"
+        "v_add_f64 %[tot], %[tot], %[t64]\n"
+        : [x0] "+v"(x[0]),
+          [x1] "+v"(x[1]),
+          [x2] "+v"(x[2]),
+          [x3] "+v"(x[3]),
+          [x4] "+v"(x[4]),
+          [x5] "+v"(x[5]),
+          [x6] "+v"(x[6]),
+          [x7] "+v"(x[7]),
+          [x8] "+v"(x[8]),
+          [x9] "+v"(x[9]),
+          [x10] "+v"(x[10]),
+          [x11] "+v"(x[11]),
+          [x12] "+v"(x[12]),
+          [x13] "+v"(x[13]),
+          [x14] "+v"(x[14]),
+          [x15] "+v"(x[15]),
+          [s0] "=&v"(s[0]),
+          [s1] "=&v"(s[1]),
+          [s2] "=&v"(s[2]),
+          [s3] "=&v"(s[3]),
+          [s4] "=&v"(s[4]),
+          [s5] "=&v"(s[5]),
+          [s6] "=&v"(s[6]),
+          [s7] "=&v"(s[7]),
+          [s8] "=&v"(s[8]),
+          [s9] "=&v"(s[9]),
+          [s10] "=&v"(s[10]),
+          [s11] "=&v"(s[11]),
+          [s12] "=&v"(s[12]),
+          [s13] "=&v"(s[13]),
+          [s14] "=&v"(s[14]),
+          [s15] "=&v"(s[15]),
+          [t64] "=&v"(t64),
+          [tot] "+v"(tot)
+        : [ui] "v"(ui), [k] "s"(k));
+}
+
 // Columns [c0, c1) of pair item cb of the row block starting at row r0
 // (row_chunks gives the chunk width; the host enumerates items with it).
 __device__ __forceinline__ void item_columns(int64_t n, int64_t r0, int64_t W, int32_t cb,
@@ -401,10 +581,14 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
         if (ua < cj + len) {
             int jj = (int)(ua - cj);
             const float4* t4 = reinterpret_cast<const float4*>(tile);
-            for (; jj + 4 * kFold <= len; jj += 4 * kFold) {
+            if constexpr (RO == 4 && R == 1 && !SAFE && !EXACT_K && !PEXP && kFold == 4) {
+                for (; jj + 16 <= len; jj += 16) pair16_r4_f32(t4 + (jj >> 2), ui[0], pc.k_hi, tot[0]);
+            } else {
+                for (; jj + 4 * kFold <= len; jj += 4 * kFold) {
 #pragma unroll
-                for (int q = 0; q < kFold; ++q) pair_b128_f32<RO, SAFE, EXACT_K, R, PEXP>(ui, t4[(jj >> 2) + q], acc, pc);
-                fold_f64<R>(acc, tot);
+                    for (int q = 0; q < kFold; ++q) pair_b128_f32<RO, SAFE, EXACT_K, R, PEXP>(ui, t4[(jj >> 2) + q], acc, pc);
+                    fold_f64<R>(acc, tot);
+                }
             }
             for (; jj + 4 <= len; jj += 4) pair_b128_f32<RO, SAFE, EXACT_K, R, PEXP>(ui, t4[jj >> 2], acc, pc);
             fold_f64<R>(acc, tot);
