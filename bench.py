@@ -55,10 +55,17 @@ def make_sample(w):
     return synth.workload_single_lognormal(w["n"], w["seed"])
 
 
+# The persistent kernel and the host code that builds its work list: a change
+# to any of them can change the traffic the counters measured.
+KERNEL_SOURCES = ("kde_device.hip", "kde_internal.h", "kde_exp2_poly.h", "kde_runtime.h", "kde_host.cpp")
+
+
 def kernel_source_sha256():
-    p = os.path.join(ROOT, "paper_1505_02100_amd", "csrc", "kde_device.hip")
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1505_02100_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload, precision):

@@ -766,6 +766,8 @@ double kde_ctx_last_device_ms(const kde_ctx* c) {
     return c->last_device_ms;
 }
 
+static_assert(NUM_STAGES == KDE_NUM_STAGES, "the timeline has one entry per stage");
+
 int kde_ctx_last_timeline(const kde_ctx* c, int64_t sample, double* ms) {
     if (!c || !ms) return set_err(KDE_EINVAL, "null context or output");
     if (sample < 0 || sample >= (int64_t)c->last_states.size())

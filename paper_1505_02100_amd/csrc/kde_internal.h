@@ -13,11 +13,11 @@ namespace kde {
 // columns [r0, n) of the upper triangle, L = n - r0 of them, and cuts them
 // into m = ceil(L / Wr) chunks of equal width w (rounded up to a multiple of
 // 4 for the b128 column reads).  Wr is the stage's chunk width W for row
-// blocks with L > n/2, W/2 for n/4 < L <= n/2 and W/4 below (not under
-// min(W, 256)): the work list runs row blocks in increasing order, so the
-// last quarter of a stage's pairs comes in smaller items and the blocks of
-// the device run out of work at nearly the same time.  Host and device
-// compute the chunks with this one function.
+// blocks with L > n/2, W/2 for n/4 < L <= n/2, W/4 for n/8 < L <= n/4 and
+// W/8 below (not under min(W, 256)): the work list runs row blocks in
+// increasing order, so the last quarter of a stage's pairs comes in smaller
+// items and the blocks of the device run out of work at nearly the same
+// time.  Host and device compute the chunks with this one function.
 __host__ __device__ inline void row_chunks(int64_t n, int64_t r0, int64_t W, int64_t* m, int64_t* w) {
     const int64_t L = n - r0;
     if (L <= 0) {
@@ -28,6 +28,7 @@ __host__ __device__ inline void row_chunks(int64_t n, int64_t r0, int64_t W, int
     int64_t Wr = W;
     if (2 * L <= n) Wr >>= 1;
     if (4 * L <= n) Wr >>= 1;
+    if (8 * L <= n) Wr >>= 1;
     const int64_t lo = W < 256 ? W : 256;
     if (Wr < lo) Wr = lo;
     *m = (L + Wr - 1) / Wr;

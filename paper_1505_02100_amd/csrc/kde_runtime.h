@@ -34,7 +34,7 @@ int hip_fail(hipError_t e, const char* what);
     } while (0)
 
 constexpr int kBlock = 256;             // threads per block of the persistent kernel
-constexpr int64_t kMomentChunk = 8192;  // elements per moment item (32 per thread)
+constexpr int64_t kMomentChunk = 2048;  // elements per moment item (8 per thread)
 constexpr uint64_t kTimeoutTicks = 20ull * 100000000ull;  // 20 s at the 100 MHz wall clock
 
 // Grow-only device buffer.

@@ -61,6 +61,7 @@ KDE_MEM_HOST = 0
 KDE_MEM_DEVICE = 1
 KDE_F64 = 0
 KDE_F32 = 1
+KDE_NUM_STAGES = 4  # entries of kde_ctx_last_timeline
 
 
 class kde_options(ctypes.Structure):
@@ -285,8 +286,9 @@ def kde_ctx_config(ctx: int) -> dict:
 
 
 def kde_ctx_last_timeline(ctx: int, sample: int = 0) -> List[float]:
-    """Milliseconds from the sample's first item to each stage's publication."""
-    ms = (_D * 4)()
+    """Milliseconds from the sample's first item to each stage's publication
+    (mean; sigma and g1; Psi6 and g2; Psi4 and h)."""
+    ms = (_D * KDE_NUM_STAGES)()
     _check(_lib.kde_ctx_last_timeline(ctx, int(sample), ms), "kde_ctx_last_timeline")
     return list(ms)
 

@@ -61,3 +61,15 @@ def test_binding_names_match_the_header():
     from paper_1505_02100_amd import kdeplugin as kp
     for name in _declared_functions():
         assert hasattr(kp, name), name
+
+
+def test_binding_constants_match_the_header():
+    # every #define KDE_* value the header states is the binding's constant of the same name
+    import re
+    from paper_1505_02100_amd import kdeplugin as kp
+    text = open(HEADER).read()
+    found = re.findall(r"^#define (KDE_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", text, flags=re.M)
+    assert ("KDE_NUM_STAGES", "4") in found
+    for name, value in found:
+        if hasattr(kp, name):
+            assert getattr(kp, name) == int(value), name
