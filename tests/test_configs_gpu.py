@@ -8,6 +8,9 @@ launch per call, device-resident samples).
   block sums over the same rectangles, and the whole result is checked
   through properties that hold at any size (scale equivariance, agreement of
   the FP32 and FP64 paths, sign invariant).
+* the serving workload's largest request, n = 4*10^6 (Student t3): sampled
+  pair items of both stages against the oracle's block sums, and properties
+  (FP32 against exact-k FP32, scale equivariance, sign invariant).
 * batch of 512 samples, n log-uniform in [256, 65536], mixed distributions:
   every h against the FP64 batch and against the oracle for all samples with
   n <= 4096 plus a few larger ones; the batch results are bitwise those of
@@ -104,6 +107,30 @@ def test_lognormal_1m_sampled_items_and_properties(kp, ctxs):
     for p in (kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT, kp.KDE_FP32_POLYEXP):
         r = ctxs[p].plugin_bandwidth(xd)
         assert _rel(r.h, r64.h) < 1e-6, (p, r.h, r64.h)
+
+
+def test_serving_largest_request_4m(kp, ctxs):
+    import torch
+    n = 4_000_000
+    x = synth.draw("t3", n, 41)
+    xd = torch.from_numpy(x).cuda()
+    r32 = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth(xd)
+    assert r32.status == 0 and r32.psi6 < 0 < r32.psi4
+    # sampled items of both pair stages at the selection's own g1 and g2 (items
+    # from the narrow end of the list: the oracle's block sums stay quick)
+    ctx = ctxs[kp.KDE_FP32_KAHAN]
+    m = ctx.psi_num_items(n)
+    for r, g in ((6, r32.g1), (4, r32.g2)):
+        for k in (m - 400, m - 50, m - 1):
+            r0, r1, c0, c1 = ctx.psi_item_geometry(n, k)
+            got = ctx.psi_range(xd, r, g, k, k + 1)
+            ref = oracle.block_sum(x, r, g, r0, r1, c0, c1)
+            bound = 2e-6 * _abs_block_sum(x, r, g, r0, r1, c0, c1) + 1e-300
+            assert abs(got - ref) <= bound, (r, k, got, ref, bound)
+    rx = ctxs[kp.KDE_FP32_KAHAN_EXACT].plugin_bandwidth(xd)
+    assert _rel(r32.h, rx.h) < 1e-6
+    r2 = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth(torch.from_numpy(2.0 * x).cuda())
+    assert _rel(r2.h, 2.0 * r32.h) < 1e-6
 
 
 @pytest.fixture(scope="module")
