@@ -308,184 +308,311 @@ __device__ __forceinline__ void fold_f64(float (&acc)[R][4], double (&tot)[R]) {
     }
 }
 
-// Step VI at R = 1 without the clamp (the default FP32 path): 16 columns
-// (four LDS b128 reads) against one row per lane, written out as a fixed
-// instruction sequence.  The operations are exactly those of pair_acc_f32 and
-// fold_f64 (per pair d = ui - xj, Y = d d, q = fma(d, d, -6), p = fma(q, Y, 3),
-// e = 2^(Y (-k)); column c of every read goes to accumulator c in read order;
-// then (a0 + a1) + (a2 + a3) into the FP64 lane total), so the result is
-// bitwise that of the loop it replaces.  Only the order differs: the
-// compiler's schedule of this step ran at 5.3e12 pairs/s on MI355X against
-// 6.0e12 for Step IV's, and timing valid orders of the step's dependency graph
-// found this one at 6.1e12 (Step IV's own compiled order was already as fast
-// as any tried).  Registers are the compiler's (every value is an operand);
-// an s_nop separates a v_exp_f32 from a VALU op that reads its result in the
-// next instruction (gfx950 needs one wait state there).
-__device__ __forceinline__ void pair16_r4_f32(const float4* t4, float ui, float k, double& tot) {
-    float x[16], s[16];
-    double t64;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const float4 v = t4[b];
-        x[4 * b] = v.x;
-        x[4 * b + 1] = v.y;
-        x[4 * b + 2] = v.z;
-        x[4 * b + 3] = v.w;
-    }
+// Step VI at R = 1 without the clamp (the default FP32 path), over cnt >= 1
+// groups of 16 columns starting at LDS byte address addr (16-byte aligned),
+// one row per lane, written out as a fixed loop.  The operations are exactly
+// those of pair_acc_f32 and fold_f64 (per pair d = ui - xj, Y = d d,
+// q = fma(d, d, -6), p = fma(q, Y, 3), e = 2^(Y (-k)); column c of every read
+// into accumulator c in read order; then (a0 + a1) + (a2 + a3) into the FP64
+// lane total), so the result is bitwise that of the generic loop.  Only the
+// order differs: the compiler's schedule of this step ran at 5.3e12 pairs/s
+// on MI355X, and timing valid orders of the step's dependency graph found this
+// one at 6.1e12.  Here the first VALU instruction sits on an 8-byte boundary,
+// the faster placement for this order.  An s_nop separates a v_exp_f32 from a
+// VALU op that reads its result in the next instruction (gfx950 needs one
+// wait state there).
+__device__ __forceinline__ void pair16_loop_r4_f32(uint32_t addr, int32_t cnt, float ui, float k, double& tot) {
     asm volatile(
-        "v_sub_f32_e32 %[x6], %[ui], %[x6]\n"
-        "v_sub_f32_e32 %[x10], %[ui], %[x10]\n"
-        "v_sub_f32_e32 %[x12], %[ui], %[x12]\n"
-        "v_sub_f32_e32 %[x1], %[ui], %[x1]\n"
-        "v_fmaak_f32 %[s0], %[x12], %[x12], 0xc0c00000\n"
-        "v_sub_f32_e32 %[x5], %[ui], %[x5]\n"
-        "v_sub_f32_e32 %[x15], %[ui], %[x15]\n"
-        "v_fmaak_f32 %[s1], %[x5], %[x5], 0xc0c00000\n"
-        "v_sub_f32_e32 %[x7], %[ui], %[x7]\n"
-        "v_sub_f32_e32 %[x11], %[ui], %[x11]\n"
-        "v_mul_f32_e32 %[x5], %[x5], %[x5]\n"
-        "v_fmaak_f32 %[s2], %[x7], %[x7], 0xc0c00000\n"
-        "v_mul_f32_e32 %[s3], %[x11], %[x11]\n"
-        "v_fmaak_f32 %[s4], %[x1], %[x1], 0xc0c00000\n"
-        "v_mul_f32_e32 %[x7], %[x7], %[x7]\n"
-        "v_mul_f32_e32 %[s5], %[x6], %[x6]\n"
-        "v_fmaak_f32 %[s1], %[s1], %[x5], 0x40400000\n"
-        "v_sub_f32_e32 %[x2], %[ui], %[x2]\n"
-        "v_sub_f32_e32 %[x13], %[ui], %[x13]\n"
-        "v_mul_f32_e32 %[s6], %[x15], %[x15]\n"
-        "v_fmaak_f32 %[s7], %[x10], %[x10], 0xc0c00000\n"
-        "v_mul_f32_e64 %[x5], %[x5], -%[k]\n"
-        "v_sub_f32_e32 %[x14], %[ui], %[x14]\n"
-        "v_mul_f32_e32 %[x10], %[x10], %[x10]\n"
-        "v_fmaak_f32 %[s2], %[s2], %[x7], 0x40400000\n"
-        "v_mul_f32_e32 %[s8], %[x13], %[x13]\n"
-        "v_mul_f32_e32 %[s9], %[x14], %[x14]\n"
-        "v_fmaak_f32 %[s10], %[x2], %[x2], 0xc0c00000\n"
-        "v_mul_f32_e32 %[x1], %[x1], %[x1]\n"
-        "v_sub_f32_e32 %[x8], %[ui], %[x8]\n"
-        "v_fmaak_f32 %[s11], %[x8], %[x8], 0xc0c00000\n"
-        "v_sub_f32_e32 %[x4], %[ui], %[x4]\n"
-        "v_sub_f32_e32 %[x3], %[ui], %[x3]\n"
-        "v_mul_f32_e32 %[s12], %[x3], %[x3]\n"
-        "v_fmaak_f32 %[x11], %[x11], %[x11], 0xc0c00000\n"
-        "v_fmaak_f32 %[x14], %[x14], %[x14], 0xc0c00000\n"
-        "v_fmaak_f32 %[s7], %[s7], %[x10], 0x40400000\n"
-        "v_mul_f32_e32 %[x12], %[x12], %[x12]\n"
-        "v_fmaak_f32 %[s13], %[x4], %[x4], 0xc0c00000\n"
-        "v_fmaak_f32 %[x13], %[x13], %[x13], 0xc0c00000\n"
-        "v_mul_f32_e32 %[x4], %[x4], %[x4]\n"
-        "v_mul_f32_e32 %[x8], %[x8], %[x8]\n"
-        "v_fmaak_f32 %[x15], %[x15], %[x15], 0xc0c00000\n"
-        "v_fmaak_f32 %[s11], %[s11], %[x8], 0x40400000\n"
-        "v_fmaak_f32 %[x3], %[x3], %[x3], 0xc0c00000\n"
-        "v_sub_f32_e32 %[x9], %[ui], %[x9]\n"
-        "v_fmaak_f32 %[s4], %[s4], %[x1], 0x40400000\n"
-        "v_fmaak_f32 %[s14], %[x9], %[x9], 0xc0c00000\n"
-        "v_fmaak_f32 %[x15], %[x15], %[s6], 0x40400000\n"
-        "v_fmaak_f32 %[x11], %[x11], %[s3], 0x40400000\n"
-        "v_sub_f32_e32 %[x0], %[ui], %[x0]\n"
-        "v_fmaak_f32 %[s0], %[s0], %[x12], 0x40400000\n"
-        "v_fmaak_f32 %[x3], %[x3], %[s12], 0x40400000\n"
-        "v_fmaak_f32 %[s15], %[x0], %[x0], 0xc0c00000\n"
-        "v_fmaak_f32 %[s13], %[s13], %[x4], 0x40400000\n"
-        "v_mul_f32_e32 %[x0], %[x0], %[x0]\n"
-        "v_fmaak_f32 %[x6], %[x6], %[x6], 0xc0c00000\n"
-        "v_fmaak_f32 %[x14], %[x14], %[s9], 0x40400000\n"
-        "v_fmaak_f32 %[x6], %[x6], %[s5], 0x40400000\n"
-        "v_fmaak_f32 %[s15], %[s15], %[x0], 0x40400000\n"
-        "v_mul_f32_e32 %[x9], %[x9], %[x9]\n"
-        "v_mul_f32_e64 %[x12], %[x12], -%[k]\n"
-        "v_mul_f32_e64 %[s12], %[s12], -%[k]\n"
-        "v_mul_f32_e64 %[x0], %[x0], -%[k]\n"
-        "v_mul_f32_e64 %[s3], %[s3], -%[k]\n"
-        "v_mul_f32_e64 %[s5], %[s5], -%[k]\n"
-        "v_mul_f32_e64 %[x7], %[x7], -%[k]\n"
-        "v_mul_f32_e64 %[x1], %[x1], -%[k]\n"
-        "v_mul_f32_e64 %[x8], %[x8], -%[k]\n"
-        "v_mul_f32_e64 %[s6], %[s6], -%[k]\n"
-        "v_mul_f32_e64 %[s9], %[s9], -%[k]\n"
-        "v_mul_f32_e64 %[x10], %[x10], -%[k]\n"
-        "v_mul_f32_e64 %[x4], %[x4], -%[k]\n"
-        "v_exp_f32_e32 %[s12], %[s12]\n"
-        "v_exp_f32_e32 %[x10], %[x10]\n"
-        "v_exp_f32_e32 %[x12], %[x12]\n"
-        "v_exp_f32_e32 %[s5], %[s5]\n"
-        "v_exp_f32_e32 %[x4], %[x4]\n"
-        "v_exp_f32_e32 %[x0], %[x0]\n"
-        "v_exp_f32_e32 %[x1], %[x1]\n"
-        "v_exp_f32_e32 %[x5], %[x5]\n"
-        "v_exp_f32_e32 %[x7], %[x7]\n"
-        "v_exp_f32_e32 %[s9], %[s9]\n"
-        "v_exp_f32_e32 %[s6], %[s6]\n"
-        "v_exp_f32_e32 %[s3], %[s3]\n"
-        "v_exp_f32_e32 %[x8], %[x8]\n"
-        "v_fmaak_f32 %[x13], %[x13], %[s8], 0x40400000\n"
-        "v_fmaak_f32 %[s14], %[s14], %[x9], 0x40400000\n"
-        "v_mul_f32_e32 %[x3], %[x3], %[s12]\n"
-        "v_mul_f32_e32 %[s12], %[s4], %[x1]\n"
-        "v_mul_f32_e32 %[s4], %[x2], %[x2]\n"
-        "v_fmaak_f32 %[x1], %[s10], %[s4], 0x40400000\n"
-        "v_fmac_f32_e32 %[x3], %[s2], %[x7]\n"
-        "v_fmac_f32_e32 %[x3], %[x11], %[s3]\n"
-        "v_fmac_f32_e32 %[s12], %[s1], %[x5]\n"
-        "v_mul_f32_e32 %[x2], %[s15], %[x0]\n"
-        "v_fmac_f32_e32 %[x2], %[s13], %[x4]\n"
-        "v_fmac_f32_e32 %[x2], %[s11], %[x8]\n"
-        "v_fmac_f32_e32 %[x3], %[x15], %[s6]\n"
-        "v_fmac_f32_e32 %[x2], %[s0], %[x12]\n"
-        "v_mul_f32_e64 %[s10], %[x9], -%[k]\n"
-        "v_mul_f32_e64 %[s2], %[s4], -%[k]\n"
-        "v_mul_f32_e64 %[x7], %[s8], -%[k]\n"
-        "v_exp_f32_e32 %[x11], %[x7]\n"
-        "v_exp_f32_e32 %[s3], %[s10]\n"
-        "v_exp_f32_e32 %[s1], %[s2]\n"
+        ".p2align 6\n"
         "s_nop 0\n"
-        "v_mul_f32_e32 %[x5], %[x1], %[s1]\n"
-        "v_fmac_f32_e32 %[x5], %[x6], %[s5]\n"
-        "v_fmac_f32_e32 %[x5], %[s7], %[x10]\n"
-        "v_fmac_f32_e32 %[x5], %[x14], %[s9]\n"
-        "v_fmac_f32_e32 %[s12], %[s14], %[s3]\n"
-        "v_fmac_f32_e32 %[s12], %[x13], %[x11]\n"
-        "v_add_f32_e32 %[s15], %[x2], %[s12]\n"
-        "v_add_f32_e32 %[x0], %[x5], %[x3]\n"
-        "v_add_f32_e32 %[s13], %[s15], %[x0]\n"
-        "v_cvt_f64_f32_e32 %[t64], %[s13]\n"
-        "v_add_f64 %[tot], %[tot], %[t64]\n"
-        : [x0] "+v"(x[0]),
-          [x1] "+v"(x[1]),
-          [x2] "+v"(x[2]),
-          [x3] "+v"(x[3]),
-          [x4] "+v"(x[4]),
-          [x5] "+v"(x[5]),
-          [x6] "+v"(x[6]),
-          [x7] "+v"(x[7]),
-          [x8] "+v"(x[8]),
-          [x9] "+v"(x[9]),
-          [x10] "+v"(x[10]),
-          [x11] "+v"(x[11]),
-          [x12] "+v"(x[12]),
-          [x13] "+v"(x[13]),
-          [x14] "+v"(x[14]),
-          [x15] "+v"(x[15]),
-          [s0] "=&v"(s[0]),
-          [s1] "=&v"(s[1]),
-          [s2] "=&v"(s[2]),
-          [s3] "=&v"(s[3]),
-          [s4] "=&v"(s[4]),
-          [s5] "=&v"(s[5]),
-          [s6] "=&v"(s[6]),
-          [s7] "=&v"(s[7]),
-          [s8] "=&v"(s[8]),
-          [s9] "=&v"(s[9]),
-          [s10] "=&v"(s[10]),
-          [s11] "=&v"(s[11]),
-          [s12] "=&v"(s[12]),
-          [s13] "=&v"(s[13]),
-          [s14] "=&v"(s[14]),
-          [s15] "=&v"(s[15]),
-          [t64] "=&v"(t64),
-          [tot] "+v"(tot)
-        : [ui] "v"(ui), [k] "s"(k));
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "1:\n"
+        "v_mov_b32_e32 v85, %[addr]\n"
+        "ds_read_b128 v[80:83], v85 offset:16\n"
+        "ds_read_b128 v[86:89], v85 offset:48\n"
+        "ds_read_b128 v[90:93], v85\n"
+        "ds_read_b128 v[94:97], v85 offset:32\n"
+        "s_add_u32 %[addr], %[addr], 64\n"
+        "s_sub_u32 %[cnt], %[cnt], 1\n"
+        "s_waitcnt lgkmcnt(0)\n"
+        "v_sub_f32_e32 v82, %[ui], v82\n"
+        "v_sub_f32_e32 v96, %[ui], v96\n"
+        "v_sub_f32_e32 v86, %[ui], v86\n"
+        "v_sub_f32_e32 v91, %[ui], v91\n"
+        "v_fmaak_f32 v99, v86, v86, 0xc0c00000\n"
+        "v_sub_f32_e32 v81, %[ui], v81\n"
+        "v_sub_f32_e32 v89, %[ui], v89\n"
+        "v_fmaak_f32 v100, v81, v81, 0xc0c00000\n"
+        "v_sub_f32_e32 v83, %[ui], v83\n"
+        "v_sub_f32_e32 v97, %[ui], v97\n"
+        "v_mul_f32_e32 v81, v81, v81\n"
+        "v_fmaak_f32 v101, v83, v83, 0xc0c00000\n"
+        "v_mul_f32_e32 v125, v97, v97\n"
+        "v_fmaak_f32 v132, v91, v91, 0xc0c00000\n"
+        "v_mul_f32_e32 v83, v83, v83\n"
+        "v_mul_f32_e32 v133, v82, v82\n"
+        "v_fmaak_f32 v100, v100, v81, 0x40400000\n"
+        "v_sub_f32_e32 v92, %[ui], v92\n"
+        "v_sub_f32_e32 v87, %[ui], v87\n"
+        "v_mul_f32_e32 v134, v89, v89\n"
+        "v_fmaak_f32 v135, v96, v96, 0xc0c00000\n"
+        "v_mul_f32_e64 v81, v81, -%[k]\n"
+        "v_sub_f32_e32 v88, %[ui], v88\n"
+        "v_mul_f32_e32 v96, v96, v96\n"
+        "v_fmaak_f32 v101, v101, v83, 0x40400000\n"
+        "v_mul_f32_e32 v136, v87, v87\n"
+        "v_mul_f32_e32 v137, v88, v88\n"
+        "v_fmaak_f32 v138, v92, v92, 0xc0c00000\n"
+        "v_mul_f32_e32 v91, v91, v91\n"
+        "v_sub_f32_e32 v94, %[ui], v94\n"
+        "v_fmaak_f32 v139, v94, v94, 0xc0c00000\n"
+        "v_sub_f32_e32 v80, %[ui], v80\n"
+        "v_sub_f32_e32 v93, %[ui], v93\n"
+        "v_mul_f32_e32 v140, v93, v93\n"
+        "v_fmaak_f32 v97, v97, v97, 0xc0c00000\n"
+        "v_fmaak_f32 v88, v88, v88, 0xc0c00000\n"
+        "v_fmaak_f32 v135, v135, v96, 0x40400000\n"
+        "v_mul_f32_e32 v86, v86, v86\n"
+        "v_fmaak_f32 v141, v80, v80, 0xc0c00000\n"
+        "v_fmaak_f32 v87, v87, v87, 0xc0c00000\n"
+        "v_mul_f32_e32 v80, v80, v80\n"
+        "v_mul_f32_e32 v94, v94, v94\n"
+        "v_fmaak_f32 v89, v89, v89, 0xc0c00000\n"
+        "v_fmaak_f32 v139, v139, v94, 0x40400000\n"
+        "v_fmaak_f32 v93, v93, v93, 0xc0c00000\n"
+        "v_sub_f32_e32 v95, %[ui], v95\n"
+        "v_fmaak_f32 v132, v132, v91, 0x40400000\n"
+        "v_fmaak_f32 v142, v95, v95, 0xc0c00000\n"
+        "v_fmaak_f32 v89, v89, v134, 0x40400000\n"
+        "v_fmaak_f32 v97, v97, v125, 0x40400000\n"
+        "v_sub_f32_e32 v90, %[ui], v90\n"
+        "v_fmaak_f32 v99, v99, v86, 0x40400000\n"
+        "v_fmaak_f32 v93, v93, v140, 0x40400000\n"
+        "v_fmaak_f32 v143, v90, v90, 0xc0c00000\n"
+        "v_fmaak_f32 v141, v141, v80, 0x40400000\n"
+        "v_mul_f32_e32 v90, v90, v90\n"
+        "v_fmaak_f32 v82, v82, v82, 0xc0c00000\n"
+        "v_fmaak_f32 v88, v88, v137, 0x40400000\n"
+        "v_fmaak_f32 v82, v82, v133, 0x40400000\n"
+        "v_fmaak_f32 v143, v143, v90, 0x40400000\n"
+        "v_mul_f32_e32 v95, v95, v95\n"
+        "v_mul_f32_e64 v86, v86, -%[k]\n"
+        "v_mul_f32_e64 v140, v140, -%[k]\n"
+        "v_mul_f32_e64 v90, v90, -%[k]\n"
+        "v_mul_f32_e64 v125, v125, -%[k]\n"
+        "v_mul_f32_e64 v133, v133, -%[k]\n"
+        "v_mul_f32_e64 v83, v83, -%[k]\n"
+        "v_mul_f32_e64 v91, v91, -%[k]\n"
+        "v_mul_f32_e64 v94, v94, -%[k]\n"
+        "v_mul_f32_e64 v134, v134, -%[k]\n"
+        "v_mul_f32_e64 v137, v137, -%[k]\n"
+        "v_mul_f32_e64 v96, v96, -%[k]\n"
+        "v_mul_f32_e64 v80, v80, -%[k]\n"
+        "v_exp_f32_e32 v140, v140\n"
+        "v_exp_f32_e32 v96, v96\n"
+        "v_exp_f32_e32 v86, v86\n"
+        "v_exp_f32_e32 v133, v133\n"
+        "v_exp_f32_e32 v80, v80\n"
+        "v_exp_f32_e32 v90, v90\n"
+        "v_exp_f32_e32 v91, v91\n"
+        "v_exp_f32_e32 v81, v81\n"
+        "v_exp_f32_e32 v83, v83\n"
+        "v_exp_f32_e32 v137, v137\n"
+        "v_exp_f32_e32 v134, v134\n"
+        "v_exp_f32_e32 v125, v125\n"
+        "v_exp_f32_e32 v94, v94\n"
+        "v_fmaak_f32 v87, v87, v136, 0x40400000\n"
+        "v_fmaak_f32 v142, v142, v95, 0x40400000\n"
+        "v_mul_f32_e32 v93, v93, v140\n"
+        "v_mul_f32_e32 v140, v132, v91\n"
+        "v_mul_f32_e32 v132, v92, v92\n"
+        "v_fmaak_f32 v91, v138, v132, 0x40400000\n"
+        "v_fmac_f32_e32 v93, v101, v83\n"
+        "v_fmac_f32_e32 v93, v97, v125\n"
+        "v_fmac_f32_e32 v140, v100, v81\n"
+        "v_mul_f32_e32 v92, v143, v90\n"
+        "v_fmac_f32_e32 v92, v141, v80\n"
+        "v_fmac_f32_e32 v92, v139, v94\n"
+        "v_fmac_f32_e32 v93, v89, v134\n"
+        "v_fmac_f32_e32 v92, v99, v86\n"
+        "v_mul_f32_e64 v138, v95, -%[k]\n"
+        "v_mul_f32_e64 v101, v132, -%[k]\n"
+        "v_mul_f32_e64 v83, v136, -%[k]\n"
+        "v_exp_f32_e32 v97, v83\n"
+        "v_exp_f32_e32 v125, v138\n"
+        "v_exp_f32_e32 v100, v101\n"
+        "s_nop 0\n"
+        "v_mul_f32_e32 v81, v91, v100\n"
+        "v_fmac_f32_e32 v81, v82, v133\n"
+        "v_fmac_f32_e32 v81, v135, v96\n"
+        "v_fmac_f32_e32 v81, v88, v137\n"
+        "v_fmac_f32_e32 v140, v142, v125\n"
+        "v_fmac_f32_e32 v140, v87, v97\n"
+        "v_add_f32_e32 v143, v92, v140\n"
+        "v_add_f32_e32 v90, v81, v93\n"
+        "v_add_f32_e32 v141, v143, v90\n"
+        "v_cvt_f64_f32_e32 v[82:83], v141\n"
+        "s_cmp_lg_u32 %[cnt], 0\n"
+        "v_add_f64 %[tot], %[tot], v[82:83]\n"
+        "s_cbranch_scc1 1b\n"
+        : [tot] "+{v[74:75]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
+        : [ui] "{v84}"(ui), [k] "s"(k)
+        : "v80", "v81", "v82", "v83", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v99", "v100", "v101", "v125", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "scc", "memory");
+}
+
+// Step IV at R = 1 without the clamp (the default FP32 path), over cnt >= 1
+// groups of 16 columns starting at LDS byte address addr (16-byte aligned),
+// one row per lane.  Per group: four b128 reads, then the operations of
+// pair_acc_f32 in its depressed form (per pair d = ui - xj, Z = fma(d, d, -5),
+// q = fma(Z, Z, -30), p = fma(q, Z, -40), e = 2^(Z (-k)); column c of every
+// read into accumulator c in read order) and of fold_f64 ((a0 + a1) + (a2 + a3)
+// into the FP64 lane total), so the result is bitwise that of the generic
+// loop.  The instructions and registers are the compiler's own code for this
+// step, whose order was as fast as any tried; the loop is written out whole
+// so that neither its order nor its placement moves with changes elsewhere
+// in the kernel.  Placement matters on MI355X: the same loop ran 12% slower
+// with its first VALU instruction on an 8-byte boundary than 4 bytes past
+// one, where the alignment directive before the loop label puts it here.
+__device__ __forceinline__ void pair16_loop_r6_f32(uint32_t addr, int32_t cnt, float ui, float k, double& tot) {
+    asm volatile(
+        ".p2align 6\n"
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "1:\n"
+        "v_mov_b32_e32 v85, %[addr]\n"
+        "ds_read_b128 v[80:83], v85\n"
+        "ds_read_b128 v[86:89], v85 offset:16\n"
+        "ds_read_b128 v[90:93], v85 offset:32\n"
+        "ds_read_b128 v[94:97], v85 offset:48\n"
+        "s_add_u32 %[addr], %[addr], 64\n"
+        "s_waitcnt lgkmcnt(0)\n"
+        "v_sub_f32_e32 v80, %[ui], v80\n"
+        "v_sub_f32_e32 v81, %[ui], v81\n"
+        "v_sub_f32_e32 v82, %[ui], v82\n"
+        "v_sub_f32_e32 v83, %[ui], v83\n"
+        "v_sub_f32_e32 v85, %[ui], v86\n"
+        "v_sub_f32_e32 v86, %[ui], v87\n"
+        "v_sub_f32_e32 v87, %[ui], v88\n"
+        "v_sub_f32_e32 v88, %[ui], v89\n"
+        "v_fmaak_f32 v80, v80, v80, 0xc0a00000\n"
+        "v_fmaak_f32 v81, v81, v81, 0xc0a00000\n"
+        "v_fmaak_f32 v82, v82, v82, 0xc0a00000\n"
+        "v_fmaak_f32 v83, v83, v83, 0xc0a00000\n"
+        "v_sub_f32_e32 v89, %[ui], v90\n"
+        "v_sub_f32_e32 v90, %[ui], v91\n"
+        "v_sub_f32_e32 v91, %[ui], v92\n"
+        "v_sub_f32_e32 v92, %[ui], v93\n"
+        "v_sub_f32_e32 v93, %[ui], v94\n"
+        "v_sub_f32_e32 v94, %[ui], v95\n"
+        "v_sub_f32_e32 v95, %[ui], v96\n"
+        "v_sub_f32_e32 v96, %[ui], v97\n"
+        "v_fmaak_f32 v85, v85, v85, 0xc0a00000\n"
+        "v_fmaak_f32 v86, v86, v86, 0xc0a00000\n"
+        "v_fmaak_f32 v87, v87, v87, 0xc0a00000\n"
+        "v_fmaak_f32 v88, v88, v88, 0xc0a00000\n"
+        "v_fmaak_f32 v97, v80, v80, 0xc1f00000\n"
+        "v_fmaak_f32 v98, v81, v81, 0xc1f00000\n"
+        "v_fmaak_f32 v99, v82, v82, 0xc1f00000\n"
+        "v_fmaak_f32 v100, v83, v83, 0xc1f00000\n"
+        "v_mul_f32_e64 v101, v80, -%[k]\n"
+        "v_mul_f32_e64 v125, v81, -%[k]\n"
+        "v_mul_f32_e64 v132, v82, -%[k]\n"
+        "v_mul_f32_e64 v133, v83, -%[k]\n"
+        "v_fmaak_f32 v89, v89, v89, 0xc0a00000\n"
+        "v_fmaak_f32 v90, v90, v90, 0xc0a00000\n"
+        "v_fmaak_f32 v91, v91, v91, 0xc0a00000\n"
+        "v_fmaak_f32 v92, v92, v92, 0xc0a00000\n"
+        "v_mul_f32_e64 v138, v85, -%[k]\n"
+        "v_mul_f32_e64 v139, v86, -%[k]\n"
+        "v_mul_f32_e64 v140, v87, -%[k]\n"
+        "v_mul_f32_e64 v141, v88, -%[k]\n"
+        "v_fmaak_f32 v80, v97, v80, 0xc2200000\n"
+        "v_fmaak_f32 v81, v98, v81, 0xc2200000\n"
+        "v_fmaak_f32 v82, v99, v82, 0xc2200000\n"
+        "v_fmaak_f32 v83, v100, v83, 0xc2200000\n"
+        "v_exp_f32_e32 v97, v101\n"
+        "v_exp_f32_e32 v98, v125\n"
+        "v_exp_f32_e32 v99, v132\n"
+        "v_exp_f32_e32 v100, v133\n"
+        "v_fmaak_f32 v93, v93, v93, 0xc0a00000\n"
+        "v_fmaak_f32 v94, v94, v94, 0xc0a00000\n"
+        "v_fmaak_f32 v95, v95, v95, 0xc0a00000\n"
+        "v_fmaak_f32 v96, v96, v96, 0xc0a00000\n"
+        "v_fmaak_f32 v134, v85, v85, 0xc1f00000\n"
+        "v_fmaak_f32 v135, v86, v86, 0xc1f00000\n"
+        "v_fmaak_f32 v136, v87, v87, 0xc1f00000\n"
+        "v_fmaak_f32 v137, v88, v88, 0xc1f00000\n"
+        "v_mul_f32_e64 v146, v89, -%[k]\n"
+        "v_mul_f32_e64 v147, v90, -%[k]\n"
+        "v_mul_f32_e64 v148, v91, -%[k]\n"
+        "v_mul_f32_e64 v149, v92, -%[k]\n"
+        "v_exp_f32_e32 v101, v138\n"
+        "v_exp_f32_e32 v125, v139\n"
+        "v_exp_f32_e32 v132, v140\n"
+        "v_exp_f32_e32 v133, v141\n"
+        "v_mul_f32_e64 v154, v93, -%[k]\n"
+        "v_mul_f32_e64 v155, v94, -%[k]\n"
+        "v_mul_f32_e64 v156, v95, -%[k]\n"
+        "v_mul_f32_e64 v157, v96, -%[k]\n"
+        "v_fmaak_f32 v85, v134, v85, 0xc2200000\n"
+        "v_fmaak_f32 v86, v135, v86, 0xc2200000\n"
+        "v_fmaak_f32 v87, v136, v87, 0xc2200000\n"
+        "v_fmaak_f32 v88, v137, v88, 0xc2200000\n"
+        "v_exp_f32_e32 v134, v146\n"
+        "v_exp_f32_e32 v135, v147\n"
+        "v_exp_f32_e32 v136, v148\n"
+        "v_exp_f32_e32 v137, v149\n"
+        "v_exp_f32_e32 v138, v154\n"
+        "v_exp_f32_e32 v139, v155\n"
+        "v_exp_f32_e32 v140, v156\n"
+        "v_exp_f32_e32 v141, v157\n"
+        "v_fmaak_f32 v142, v89, v89, 0xc1f00000\n"
+        "v_fmaak_f32 v143, v90, v90, 0xc1f00000\n"
+        "v_fmaak_f32 v144, v91, v91, 0xc1f00000\n"
+        "v_fmaak_f32 v145, v92, v92, 0xc1f00000\n"
+        "v_fma_f32 v80, v80, v97, 0\n"
+        "v_fma_f32 v81, v81, v98, 0\n"
+        "v_fma_f32 v82, v82, v99, 0\n"
+        "v_fma_f32 v83, v83, v100, 0\n"
+        "v_fmaak_f32 v150, v93, v93, 0xc1f00000\n"
+        "v_fmaak_f32 v151, v94, v94, 0xc1f00000\n"
+        "v_fmaak_f32 v152, v95, v95, 0xc1f00000\n"
+        "v_fmaak_f32 v153, v96, v96, 0xc1f00000\n"
+        "v_fmaak_f32 v89, v142, v89, 0xc2200000\n"
+        "v_fmaak_f32 v90, v143, v90, 0xc2200000\n"
+        "v_fmaak_f32 v91, v144, v91, 0xc2200000\n"
+        "v_fmaak_f32 v92, v145, v92, 0xc2200000\n"
+        "v_fmac_f32_e32 v80, v85, v101\n"
+        "v_fmac_f32_e32 v81, v86, v125\n"
+        "v_fmac_f32_e32 v82, v87, v132\n"
+        "v_fmac_f32_e32 v83, v88, v133\n"
+        "v_fmaak_f32 v93, v150, v93, 0xc2200000\n"
+        "v_fmaak_f32 v94, v151, v94, 0xc2200000\n"
+        "v_fmaak_f32 v95, v152, v95, 0xc2200000\n"
+        "v_fmaak_f32 v96, v153, v96, 0xc2200000\n"
+        "v_fmac_f32_e32 v80, v89, v134\n"
+        "v_fmac_f32_e32 v81, v90, v135\n"
+        "v_fmac_f32_e32 v82, v91, v136\n"
+        "v_fmac_f32_e32 v83, v92, v137\n"
+        "v_fmac_f32_e32 v80, v93, v138\n"
+        "v_fmac_f32_e32 v81, v94, v139\n"
+        "v_fmac_f32_e32 v82, v95, v140\n"
+        "v_fmac_f32_e32 v83, v96, v141\n"
+        "v_add_f32_e32 v80, v80, v81\n"
+        "v_add_f32_e32 v81, v82, v83\n"
+        "s_sub_u32 %[cnt], %[cnt], 1\n"
+        "v_add_f32_e32 v80, v80, v81\n"
+        "v_cvt_f64_f32_e32 v[80:81], v80\n"
+        "s_cmp_lg_u32 %[cnt], 0\n"
+        "v_add_f64 %[tot], %[tot], v[80:81]\n"
+        "s_cbranch_scc1 1b\n"
+        : [tot] "+{v[74:75]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
+        : [ui] "{v84}"(ui), [k] "s"(k)
+        : "v80", "v81", "v82", "v83", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101", "v125", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "v144", "v145", "v146", "v147", "v148", "v149", "v150", "v151", "v152", "v153", "v154", "v155", "v156", "v157", "scc", "memory");
 }
 
 // Columns [c0, c1) of pair item cb of the row block starting at row r0
@@ -581,8 +708,16 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
         if (ua < cj + len) {
             int jj = (int)(ua - cj);
             const float4* t4 = reinterpret_cast<const float4*>(tile);
-            if constexpr (RO == 4 && R == 1 && !SAFE && !EXACT_K && !PEXP && kFold == 4) {
-                for (; jj + 16 <= len; jj += 16) pair16_r4_f32(t4 + (jj >> 2), ui[0], pc.k_hi, tot[0]);
+            if constexpr ((RO == 4 || RO == 6) && R == 1 && !SAFE && !EXACT_K && !PEXP && kFold == 4) {
+                // jj is a multiple of 64 here (row blocks, waves and chunk
+                // starts all are), so the group reads are 16-byte aligned
+                const int32_t groups = (len - jj) >> 4;
+                if (groups > 0) {
+                    const uint32_t lds = (uint32_t)(size_t)((__attribute__((address_space(3))) float*)tile) + 4u * (uint32_t)jj;
+                    if constexpr (RO == 4) pair16_loop_r4_f32(lds, groups, ui[0], pc.k_hi, tot[0]);
+                    else pair16_loop_r6_f32(lds, groups, ui[0], pc.k_hi, tot[0]);
+                    jj += groups << 4;
+                }
             } else {
                 for (; jj + 4 * kFold <= len; jj += 4 * kFold) {
 #pragma unroll

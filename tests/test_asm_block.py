@@ -1,16 +1,20 @@
-"""The fixed-order Step VI block (`pair16_r4_f32` in kde_device.hip) read back
-from the source and executed instruction by instruction on the CPU.
+"""The fixed-order loops of Steps IV and VI (`pair16_loop_r6_f32` and
+`pair16_loop_r4_f32` in kde_device.hip) read back from the source and executed
+instruction by instruction on the CPU.
 
-The block is the 16-column step of Step VI written out as gfx950 assembly
-(equation (7) with the Gaussian kernel's fourth derivative, He4(u) =
-u^4 - 6u^2 + 3, and exp(-u^2/2) = 2^(-k u^2)).  This test checks its data flow
+Each loop runs the 16-column step of its stage, written out as gfx950 assembly
+(equations (6)-(7) with the Gaussian kernel's sixth and fourth derivatives,
+He6 in the depressed form (Z^2 - 30) Z - 40 with Z = u^2 - 5, He4(u) =
+u^4 - 6u^2 + 3, and exp(-u^2/2) = 2^(-k u^2)).  This test checks their data flow
 without a GPU: every operand it reads holds the value the per-pair formula
 says it should, the four column accumulators take their terms in read order,
 and the fold into the FP64 total is (a0 + a1) + (a2 + a3).  Both sides use the
 same FP32 arithmetic model (exact products rounded once, 2^x rounded to FP32),
 so any dropped term, wrong register or misordered accumulation fails it.
-It also checks the one wait state gfx950 needs between a transcendental
-result and a VALU op that reads it in the next instruction.
+The loop control is modelled too (64 bytes of LDS per group, cnt groups,
+nothing read past the last one).  It also checks the one wait state gfx950
+needs between a transcendental result and a VALU op that reads it in the next
+instruction, and where each loop's first VALU op lands within 64 bytes.
 """
 import os
 import re
@@ -33,6 +37,16 @@ def block_lines(name):
     return [m.group(1) for m in re.finditer(r'"([^"]*)\\n"', body)]
 
 
+def operand(tok):
+    """Register-file key of an operand: %[name] or a physical VGPR (range)."""
+    m = re.fullmatch(r"%\[(\w+)\]", tok)
+    if m:
+        return m.group(1)
+    if re.fullmatch(r"v\d+|v\[\d+:\d+\]", tok):
+        return tok
+    return None
+
+
 def fma32(a, b, c):
     # one rounding of the exact a*b + c (through a correctly rounded double)
     return f32(float(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c))))
@@ -48,41 +62,69 @@ def literal(tok):
     return f32(float(tok))
 
 
-def execute(lines, x, ui, k, tot):
-    reg = {f"x{j}": f32(x[j]) for j in range(16)}
-    reg.update(ui=f32(ui), k=f32(k), tot=float(tot))
+def execute(lines, x, ui, k, tot, cnt=None):
+    """Run a block on one lane.  x is the LDS tile (FP32 values from byte
+    address 0); a whole-loop block runs cnt groups of 16 columns from there."""
+    reg = {f"x{j}": f32(x[j]) for j in range(min(16, len(x)))}
+    reg.update(ui=f32(ui), k=f32(k), tot=float(tot), addr=0, cnt=cnt, scc=0)
+    labels = {l[:-1]: i for i, l in enumerate(lines) if l.endswith(":")}
 
     def val(tok):
         neg = tok.startswith("-")
         tok = tok.lstrip("-")
-        m = re.fullmatch(r"%\[(\w+)\]", tok)
-        v = reg[m.group(1)] if m else literal(tok)
+        key = operand(tok)
+        v = reg[key] if key else literal(tok)
         return -v if neg else v
 
-    for line in lines:
+    pc, steps = 0, 0
+    while pc < len(lines):
+        line = lines[pc]
+        pc += 1
+        steps += 1
+        assert steps < 100000
         op, _, rest = line.partition(" ")
-        if op == "s_nop":
-            continue
         t = [a.strip() for a in rest.split(",")]
-        d = re.fullmatch(r"%\[(\w+)\]", t[0]).group(1)
-        if op.startswith("v_sub_f32"):
-            reg[d] = f32(val(t[1]) - val(t[2]))
-        elif op.startswith("v_add_f32"):
-            reg[d] = f32(val(t[1]) + val(t[2]))
-        elif op.startswith("v_mul_f32"):
-            reg[d] = f32(val(t[1]) * val(t[2]))
-        elif op.startswith("v_fmaak_f32") or op.startswith("v_fma_f32"):
-            reg[d] = fma32(val(t[1]), val(t[2]), val(t[3]))
-        elif op.startswith("v_fmac_f32"):
-            reg[d] = fma32(val(t[1]), val(t[2]), reg[d])
-        elif op.startswith("v_exp_f32"):
-            reg[d] = exp2_32(val(t[1]))
-        elif op.startswith("v_cvt_f64_f32"):
-            reg[d] = float(val(t[1]))
-        elif op.startswith("v_add_f64"):
-            reg[d] = reg["tot"] + reg["t64"]
+        if op.endswith(":") or op in ("s_nop", "s_waitcnt", ".p2align"):
+            continue
+        if op == "s_add_u32":
+            reg[operand(t[0])] = int(reg[operand(t[1])]) + int(t[2])
+        elif op == "s_sub_u32":
+            reg[operand(t[0])] = int(reg[operand(t[1])]) - int(t[2])
+        elif op == "s_cmp_lg_u32":
+            reg["scc"] = int(reg[operand(t[0])] != int(t[1]))
+        elif op == "s_cbranch_scc1":
+            if reg["scc"]:
+                pc = labels[t[0][:-1]]
+        elif op == "v_mov_b32_e32" and t[1] == "%[addr]":
+            reg[t[0]] = reg["addr"]
+        elif op == "ds_read_b128":
+            # four consecutive values at the address register plus the offset
+            m = re.fullmatch(r"v\[(\d+):(\d+)\], (v\d+)(?: offset:(\d+))?", rest.strip())
+            first, byte = int(m.group(1)), reg[m.group(3)] + int(m.group(4) or 0)
+            assert byte % 16 == 0
+            for c in range(4):
+                reg[f"v{first + c}"] = f32(x[byte // 4 + c])
         else:
-            raise AssertionError(f"unexpected instruction {op}")
+            d = operand(t[0])
+            if op.startswith("v_sub_f32"):
+                reg[d] = f32(val(t[1]) - val(t[2]))
+            elif op.startswith("v_add_f32"):
+                reg[d] = f32(val(t[1]) + val(t[2]))
+            elif op.startswith("v_mul_f32"):
+                reg[d] = f32(val(t[1]) * val(t[2]))
+            elif op.startswith("v_fmaak_f32") or op.startswith("v_fma_f32"):
+                reg[d] = fma32(val(t[1]), val(t[2]), val(t[3]))
+            elif op.startswith("v_fmac_f32"):
+                reg[d] = fma32(val(t[1]), val(t[2]), reg[d])
+            elif op.startswith("v_exp_f32"):
+                reg[d] = exp2_32(val(t[1]))
+            elif op.startswith("v_cvt_f64_f32"):
+                reg[d] = float(val(t[1]))
+            elif op.startswith("v_add_f64"):
+                reg[d] = val(t[1]) + val(t[2])
+            else:
+                raise AssertionError(f"unexpected instruction {op}")
+    assert cnt is None or reg["cnt"] == 0
     return reg["tot"]
 
 
@@ -99,37 +141,64 @@ def step_vi_reference(x, ui, k, tot):
     return float(tot) + float(f32(f32(acc[0] + acc[1]) + f32(acc[2] + acc[3])))
 
 
-def test_step_vi_block_computes_the_pair_terms():
-    lines = block_lines("pair16_r4_f32")
+def step_iv_reference(x, ui, k, tot):
+    acc = [None] * 4
+    for j in range(16):
+        d = f32(f32(ui) - f32(x[j]))
+        z = fma32(d, d, f32(-5.0))
+        q = fma32(z, z, f32(-30.0))
+        p = fma32(q, z, f32(-40.0))
+        e = exp2_32(f32(z * f32(-k)))
+        c = j % 4
+        acc[c] = fma32(p, e, f32(0.0)) if acc[c] is None else fma32(p, e, acc[c])
+    return float(tot) + float(f32(f32(acc[0] + acc[1]) + f32(acc[2] + acc[3])))
+
+
+R6, R4 = "pair16_loop_r6_f32", "pair16_loop_r4_f32"
+K = f32(np.log2(np.e) / 2)
+
+
+def run_groups(ref, x, ui, k, tot, cnt):
+    for g in range(cnt):
+        tot = ref(x[16 * g:16 * g + 16], ui, k, tot)
+    return tot
+
+
+@pytest.mark.parametrize("name,ref,seed", [(R6, step_iv_reference, 5), (R4, step_vi_reference, 7)])
+def test_loop_computes_the_pair_terms(name, ref, seed):
+    lines = block_lines(name)
     assert sum(l.startswith("v_exp_f32") for l in lines) == 16
-    rng = np.random.default_rng(7)
-    k = f32(np.log2(np.e) / 2)
-    for _ in range(200):
-        x = rng.normal(0.0, 2.0, 16).astype(np.float32)
+    assert sum(l.startswith("ds_read_b128") for l in lines) == 4
+    rng = np.random.default_rng(seed)
+    for trial in range(120):
+        cnt = 1 + trial % 4
+        # values past the last group are NaN: a read beyond it would show
+        x = np.concatenate([rng.normal(0.0, 2.0, 16 * cnt), np.full(16, np.nan)]).astype(np.float32)
         ui = f32(rng.normal(0.0, 2.0))
         tot = rng.normal()
-        assert execute(lines, x, ui, k, tot) == step_vi_reference(x, ui, k, tot)
+        assert execute(lines, x, ui, K, tot, cnt) == run_groups(ref, x, ui, K, tot, cnt)
 
 
-def test_step_vi_block_detects_a_planted_error():
+def test_step_vi_loop_detects_a_planted_error():
     # the check above is not vacuous: reading the wrong register changes the result
-    lines = block_lines("pair16_r4_f32")
+    lines = block_lines(R4)
     i = next(i for i, l in enumerate(lines) if l.startswith("v_fmac_f32"))
-    ops = lines[i].split(", ")
-    ops[1], ops[2] = ops[2], ops[1]           # harmless swap (product is commutative)
-    same = lines[:i] + [", ".join(ops)] + lines[i + 1:]
-    wrong = lines[:i] + [lines[i].replace(ops[2], "%[x0]")] + lines[i + 1:]
+    op, _, rest = lines[i].partition(" ")
+    d, a, b = [t.strip() for t in rest.split(",")]
+    same = lines[:i] + [f"{op} {d}, {b}, {a}"] + lines[i + 1:]     # product is commutative
+    wrong = lines[:i] + [f"{op} {d}, {a}, {a}"] + lines[i + 1:]    # one factor read twice
     rng = np.random.default_rng(1)
-    x = rng.normal(0.0, 1.0, 16).astype(np.float32)
-    k = f32(np.log2(np.e) / 2)
-    ref = step_vi_reference(x, f32(0.3), k, 0.0)
-    assert execute(same, x, f32(0.3), k, 0.0) == ref
-    assert execute(wrong, x, f32(0.3), k, 0.0) != ref
+    x = rng.normal(0.0, 1.0, 32).astype(np.float32)
+    ref = run_groups(step_vi_reference, x, f32(0.3), K, 0.0, 2)
+    assert execute(same, x, f32(0.3), K, 0.0, 2) == ref
+    assert execute(wrong, x, f32(0.3), K, 0.0, 2) != ref
 
 
-def test_transcendental_results_are_not_read_in_the_next_instruction():
-    lines = block_lines("pair16_r4_f32")
-    for a, b in zip(lines, lines[1:]):
+@pytest.mark.parametrize("name", [R6, R4])
+def test_transcendental_results_are_not_read_in_the_next_instruction(name):
+    lines = block_lines(name)
+    body = [l for l in lines if not l.endswith(":") and not l.startswith(".")]
+    for a, b in zip(body, body[1:] + body[:1]):     # the loop's back edge included
         if not a.startswith("v_exp_f32") or b.startswith(("v_exp_f32", "s_nop")):
             continue
         dst = a.split()[1].rstrip(",")
@@ -138,18 +207,59 @@ def test_transcendental_results_are_not_read_in_the_next_instruction():
         assert dst not in reads, (a, b)
 
 
-def test_block_operands_are_declared():
+# encoded sizes (bytes) of the instructions that precede the first VALU op
+HEAD_BYTES = {"v_mov_b32_e32": 4, "ds_read_b128": 8, "s_add_u32": 4, "s_sub_u32": 4, "s_waitcnt": 4}
+
+
+@pytest.mark.parametrize("name,mod64", [(R6, 60), (R4, 0)])
+def test_loop_body_placement(name, mod64):
+    # the block starts on a 64-byte boundary; the padding before the loop
+    # label runs once per call, and the first VALU op of the body lands where
+    # each order was timed fastest
+    lines = block_lines(name)
+    assert lines[0] == ".p2align 6"
+    label = lines.index("1:")
+    assert all(l == "s_nop 0" for l in lines[1:label])
+    off = 4 * (label - 1)
+    for l in lines[label + 1:]:
+        op = l.split()[0]
+        if op.startswith("v_") and op != "v_mov_b32_e32":
+            break
+        assert op in HEAD_BYTES, l
+        assert op != "s_add_u32" or l.endswith(", 64")     # inline constant, no literal
+        off += HEAD_BYTES[op]
+    assert off % 64 == mod64
+
+
+@pytest.mark.parametrize("name", [R6, R4])
+def test_block_operands_are_declared(name):
     text = open(SRC).read()
-    start = text.index("void pair16_r4_f32(")
+    start = text.index(f"void {name}(")
     end = text.index("\n}\n", start)
     fn = text[start:end]
     used = set(re.findall(r"%\[(\w+)\]", fn))
     declared = set(re.findall(r"\[(\w+)\] \"", fn))
     assert used <= declared, used - declared
-    # outputs written before some input is last read must be early-clobber
-    for name in used:
-        if name.startswith("s"):
-            assert f'[{name}] "=&v"' in fn, name
+    # operands the block writes are read-write
+    lines = block_lines(name)
+    for l in lines:
+        m = re.match(r"[sv]_\w+ %\[(\w+)\],", l)
+        if m and not l.startswith("s_cmp"):
+            assert re.search(rf'\[{m.group(1)}\] "\+', fn), l
+    # physical registers the block writes are clobbered, or are its pinned operands
+    pinned = set(re.findall(r'"\+?\{(v\d+|v\[\d+:\d+\])\}"', fn))
+    for line in lines:
+        op, _, rest = line.partition(" ")
+        if not op.startswith(("v_", "ds_read")):
+            continue
+        dst = rest.split(",")[0].strip()
+        m = re.fullmatch(r"v(\d+)|v\[(\d+):(\d+)\]", dst)
+        if not m:
+            continue
+        regs = [int(m.group(1))] if m.group(1) else list(range(int(m.group(2)), int(m.group(3)) + 1))
+        for r in regs:
+            assert f'"v{r}"' in fn or dst in pinned, (name, line)
+    assert '"scc"' in fn
 
 
 if __name__ == "__main__":
