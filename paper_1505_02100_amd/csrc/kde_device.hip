@@ -1228,6 +1228,10 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
     uint32_t pend_cnt = 0;
     __shared__ int64_t pacc[4];
     if (tid < 4) pacc[tid] = 0;
+    // the view of the last item's (sample, stage): consecutive items of one
+    // stage share it, so it is read again only when the pair changes
+    View d = {};
+    int32_t d_ds = -1, d_stage = -1;
     for (;;) {
         if (tid == 0) {
             sh_ticket = next;
@@ -1246,7 +1250,11 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         }
         if (!have) break;
 
-        const View d = load_view(A.descs + it.ds, it.stage);
+        if (it.ds != d_ds || it.stage != d_stage) {
+            d = load_view(A.descs + it.ds, it.stage);
+            d_ds = it.ds;
+            d_stage = it.stage;
+        }
         State* st = A.states + it.ds;
 
         if (tid == 0) {
