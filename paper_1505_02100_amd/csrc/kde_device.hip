@@ -1188,13 +1188,19 @@ __device__ void complete_items(const LaunchArgs& A, int32_t ds, const View& d, S
 
 // Memory-model cost on a multi-XCD device: an agent-scope release writes
 // back the XCD's L2 and an agent-scope acquire invalidates it, for every CU of
-// that XCD.  The loop therefore (i) fetches the next ticket with a relaxed
-// atomic one item ahead, (ii) waits with relaxed polling and issues one
-// acquire per (block, sample, stage) it has not seen published yet, caching
-// the published scalars in LDS, and (iii) counts its finished items of one
-// run of (sample, stage) items with a single release read-modify-write, as
-// soon as its prefetched next ticket lies past the run (or there is none);
-// only a stage's finaliser acquires the slots.
+// that XCD.  The loop therefore (i) takes tickets with a relaxed atomic,
+// (ii) waits with relaxed polling and issues one acquire per (block, sample,
+// stage) it has not seen published yet, caching the published scalars in
+// LDS, and (iii) counts its finished items of one run of (sample, stage)
+// items with a single release read-modify-write, as soon as its next ticket
+// lies past the run (or there is none); only a stage's finaliser acquires
+// the slots.
+//
+// A block takes its next ticket when it has finished an item, not when it
+// starts one: the three blocks on a CU progress at different rates (the
+// oldest waves issue first), and a ticket taken a whole item ahead by a slow
+// block left that item waiting while faster blocks ran dry at the end of
+// every stage.
 //
 // Progress.  A block holds uncounted items of one (sample, stage) only, and
 // it counts them before it starts an item of another (sample, stage) (the
@@ -1216,7 +1222,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
     __shared__ Published sh_pub;  // a finaliser's values, for its replica writers
 
     const int tid = threadIdx.x;
-    uint32_t next = 0;  // thread 0: prefetched ticket
+    uint32_t next = 0;  // thread 0: the block's next ticket
     if (tid == 0) {
         next = atomicAdd(A.ticket, 1u);
         sh_cds = -1;
@@ -1235,7 +1241,6 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
     for (;;) {
         if (tid == 0) {
             sh_ticket = next;
-            if (next < A.n_items) next = atomicAdd(A.ticket, 1u);
         }
         __syncthreads();
         const uint32_t t = sh_ticket;
@@ -1355,6 +1360,7 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
                 s.aux = aux;
                 A.slots[it.slot] = s;
             }
+            next = atomicAdd(A.ticket, 1u);
             sh_flush = next >= (uint32_t)it.run_end ? 1 : 0;
         }
         pend_ds = it.ds;
