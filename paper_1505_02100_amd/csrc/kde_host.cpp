@@ -99,11 +99,12 @@ int64_t target_items_for(const kde_ctx* c, int64_t n) {
     while (lg < 62 && ((int64_t)2 << lg) <= n) ++lg;
     for (int b = lg; b >= 0; --b)
         if (c->bucket_target[b] > 0) return c->bucket_target[b];
-    // about n/10 items per stage, i.e. chunks of about n/51 columns (rounded
-    // up to a power of two) for 256-row tiles; at least 1024 items so small
-    // samples still spread over the device, at most 65536 so the work list
-    // stays small (beyond n = 2^18 the count hardly matters)
-    return std::min<int64_t>(65536, std::max<int64_t>(1024, (n + 9) / 10));
+    // about n/32 items per stage, i.e. chunks of about n/16 columns (rounded
+    // up to a power of two) for 256-row tiles; up to n = 2048 the narrowest
+    // chunks (1024 items), and at most 65536 so the work list stays small
+    // (beyond n = 2^18 the count hardly matters)
+    if (n <= 2048) return 1024;
+    return std::min<int64_t>(65536, (n + 31) / 32);
 }
 
 // Tune table (written by kde_autotune): a small JSON object
