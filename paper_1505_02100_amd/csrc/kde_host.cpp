@@ -3,8 +3,8 @@
 // A context owns a small cache of "plans".  A plan is everything one launch
 // of the persistent kernel needs for a fixed problem shape: the ordered work
 // list, the per-sample descriptors, state records, partial-sum slots, the
-// work ticket, and a hipGraph (init kernel + persistent kernel) that is
-// replayed whenever the same shape comes back.  Only the descriptors (sample
+// work ticket, and a hipGraph (init kernel + persistent kernel + state
+// read-back) that is replayed whenever the same shape comes back.  Only the descriptors (sample
 // pointers) are refreshed between replays, and only when they changed.
 #include <hip/hip_runtime.h>
 

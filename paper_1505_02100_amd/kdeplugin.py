@@ -206,7 +206,7 @@ class _Samples:
                 self.n = x.numel()
                 self.mem = KDE_MEM_DEVICE
                 self.dtype = KDE_F64 if x.dtype == _torch().float64 else KDE_F32
-                self.stream = _torch().cuda.current_stream(x.device).cuda_stream
+                self.stream = _current_stream(x.device)
                 return
             x = x.detach().cpu().numpy()
         a = np.asarray(x)
@@ -224,6 +224,16 @@ class _Samples:
 def _torch():
     import torch
     return torch
+
+
+def _current_stream(device) -> int:
+    """The raw HIP stream torch currently uses on `device` (the call is
+    ordered after the tensor's producers on that stream)."""
+    t = _torch()
+    raw = getattr(t._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return raw(device.index if device.index is not None else t.cuda.current_device())
+    return t.cuda.current_stream(device).cuda_stream
 
 
 def _is_torch(x) -> bool:
@@ -377,7 +387,7 @@ def kde_eval_ex(ctx: int, x, y, h: float):
         if yy.dtype != torch.float64:
             raise TypeError("evaluation points must be float64")
         out = torch.empty_like(yy)
-        stream = torch.cuda.current_stream(yy.device).cuda_stream
+        stream = _current_stream(yy.device)
         _check(_lib.kde_eval_ex(ctx, s.ptr, s.n, s.mem, s.dtype, yy.data_ptr(), yy.numel(), KDE_MEM_DEVICE,
                                 float(h), stream, out.data_ptr()), "kde_eval_ex")
         return out
