@@ -55,9 +55,12 @@
 // FP64 pair arithmetic is the plain printed form: t = y^2,
 // p = ((t - 15) t + 45) t - 15 (resp. (t - 6) t + 3), exp(-t/2), FP64 sums.
 //
-// Cross-block reduction is deterministic.  A moment item writes its own
-// slot, and the block that completes a moment stage's last item (atomic
-// counter) sums the stage's slots in index order.  A pair item's FP64
+// Cross-block reduction is deterministic.  Step I takes one pass: a moment
+// item writes its chunk's sum, squared deviations from the chunk's own mean,
+// minimum and maximum into two slots, and the block that completes the last
+// chunk (atomic counter) merges the chunks in a fixed order with the update
+// of Chan, Golub and LeVeque and publishes both Step I stages at once (the
+// second stage's items only count).  A pair item's FP64
 // partial is added exactly, as a 128-bit fixed-point integer, into the
 // block's accumulator, which goes into the stage's accumulator with
 // integer atomics; integer addition does not depend on order, so the sum
@@ -174,50 +177,94 @@ __device__ __forceinline__ double block_max(double v, double* red) {
     return m;
 }
 
+template <int BLOCK>
+__device__ __forceinline__ double block_max_signed(double v, double* red) {
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double m = v;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < BLOCK / WAVE; ++w) m = fmax(m, red[w]);
+    }
+    __syncthreads();
+    return m;  // valid in thread 0
+}
+
 // ------------------------------------------------------------- moments
 // Each thread reads U values per round so that the loads of a round are in
 // flight together; per-thread order is fixed, so the result is deterministic.
 constexpr int kMomentUnroll = 8;
 
+// Step I in one pass over chunk chunk_idx: the sum of x - x[0] (every chunk
+// takes the same shift, so the chunk means the merge compares are small
+// numbers and keep their accuracy when the sample sits far from 0), the
+// sum of squared deviations from the chunk's own mean (the data are read
+// again for that, from cache), and the chunk's minimum and maximum.
+// Per-thread order is fixed, so the result is deterministic.  All four are
+// valid in thread 0.
 template <int BLOCK>
-__device__ double moment_sum(const View& d, int32_t chunk_idx, double* red) {
+__device__ void moment_stats(const View& d, int32_t chunk_idx, double* red, double* out_sum, double* out_m2,
+                             double* out_min, double* out_max) {
     const int64_t a = (int64_t)chunk_idx * d.chunk;
     const int64_t b = min(a + (int64_t)d.chunk, d.n);
-    double s = 0.0;
+    const double x0 = load_x(d.x, d.dtype, 0);
+    double s = 0.0, lo = INFINITY, hi = -INFINITY;
     for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += (int64_t)BLOCK * kMomentUnroll) {
         double v[kMomentUnroll];
 #pragma unroll
         for (int u = 0; u < kMomentUnroll; ++u) {
             const int64_t i = i0 + (int64_t)u * BLOCK;
-            v[u] = i < b ? load_x(d.x, d.dtype, i) : 0.0;
+            v[u] = i < b ? load_x(d.x, d.dtype, i) : x0;
         }
 #pragma unroll
-        for (int u = 0; u < kMomentUnroll; ++u) s += v[u];
+        for (int u = 0; u < kMomentUnroll; ++u) {
+            s += v[u] - x0;
+            lo = fmin(lo, v[u]);
+            hi = fmax(hi, v[u]);
+        }
     }
-    return block_sum<BLOCK>(s, red);
+    const double sum = block_sum<BLOCK>(s, red);
+    if (threadIdx.x == 0) red[0] = sum / (double)(b - a);
+    __syncthreads();
+    const double mc = red[0];
+    __syncthreads();
+    double q = 0.0;
+    for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += (int64_t)BLOCK * kMomentUnroll) {
+        double v[kMomentUnroll];
+#pragma unroll
+        for (int u = 0; u < kMomentUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * BLOCK;
+            v[u] = i < b ? (load_x(d.x, d.dtype, i) - x0) - mc : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kMomentUnroll; ++u) q = fma(v[u], v[u], q);
+    }
+    *out_sum = sum;
+    *out_m2 = block_sum<BLOCK>(q, red);
+    *out_min = -block_max_signed<BLOCK>(-lo, red);
+    *out_max = block_max_signed<BLOCK>(hi, red);
 }
 
-template <int BLOCK>
-__device__ void moment_ssq(const View& d, int32_t chunk_idx, double mean, double* red,
-                           double* out_ssq, double* out_max) {
-    const int64_t a = (int64_t)chunk_idx * d.chunk;
-    const int64_t b = min(a + (int64_t)d.chunk, d.n);
-    double s = 0.0, m = 0.0;
-    for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += (int64_t)BLOCK * kMomentUnroll) {
-        double v[kMomentUnroll];
-#pragma unroll
-        for (int u = 0; u < kMomentUnroll; ++u) {
-            const int64_t i = i0 + (int64_t)u * BLOCK;
-            v[u] = i < b ? load_x(d.x, d.dtype, i) - mean : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kMomentUnroll; ++u) {
-            s = fma(v[u], v[u], s);
-            m = fmax(m, fabs(v[u]));
-        }
+// Merge of two (count, mean, sum of squared deviations) triples, the
+// pairwise update of Chan, Golub and LeVeque: exact in real arithmetic and
+// stable in floating point whatever the spread of the two means.
+__device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, double nb, double meanb,
+                                           double m2b) {
+    if (nb == 0.0) return;
+    if (n == 0.0) {
+        n = nb;
+        mean = meanb;
+        m2 = m2b;
+        return;
     }
-    *out_ssq = block_sum<BLOCK>(s, red);
-    *out_max = block_max<BLOCK>(m, red);
+    const double t = n + nb;
+    const double delta = meanb - mean;
+    mean += delta * (nb / t);
+    m2 += m2b + delta * delta * (n * nb / t);
+    n = t;
 }
 
 // ---------------------------------------------------- FP32 pair evaluation
@@ -1104,8 +1151,9 @@ __device__ __forceinline__ double fx_value(const int64_t (&a)[4]) {
 
 // Completion of `cnt` items of one (sample, stage) whose slots this block
 // has written: one release read-modify-write on the stage's counter.  The
-// block that brings the counter to the stage's item count sums the stage's
-// slots in index order (Neumaier) and runs the stage's scalar formulas.
+// block that brings the counter to the stage's item count merges Step I's
+// chunks (first stage) or reads the exact pair sum, and runs the stage's
+// scalar formulas.
 template <int PREC, int BLOCK>
 __device__ void complete_items(const LaunchArgs& A, int32_t ds, const View& d, State* st, int32_t stage,
                                uint32_t cnt, int64_t (&pacc)[4], double* red, int32_t* sh_last,
@@ -1126,7 +1174,9 @@ __device__ void complete_items(const LaunchArgs& A, int32_t ds, const View& d, S
         *sh_last = (old + cnt == (uint32_t)d.cnt) ? 1 : 0;
     }
     __syncthreads();
-    if (*sh_last) {
+    // Step I's second stage has no work of its own: the first stage's
+    // finaliser published it (its items only count)
+    if (*sh_last && stage != ST_SSQ) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         Prior pr{};
         int64_t a[4] = {0, 0, 0, 0};
@@ -1137,50 +1187,93 @@ __device__ void complete_items(const LaunchArgs& A, int32_t ds, const View& d, S
                 for (int q = 0; q < 4; ++q)
                     a[q] = __hip_atomic_load(&st->acc[stage - ST_PSI6][q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        double tot = 0.0, mx = 0.0;
-        if (stage < ST_PSI6) {
-            // each thread sums its slots k = tid + BLOCK q in q order
-            // (Neumaier), loading U of them at a time so the loads overlap;
-            // only Step I's second pass has an aux part
-            const int64_t base = d.base;
-            const int32_t n_slots = d.cnt;
-            constexpr int U = 8;
-            double s = 0.0, c = 0.0, m = 0.0;
-            for (int32_t k0 = tid; k0 < n_slots; k0 += BLOCK * U) {
-                double buf[U];
+        double tot = 0.0, mx = 0.0, mean = 0.0;
+        if (stage == ST_SUM) {
+            // Step I: every thread merges a contiguous range of chunks in
+            // index order, the lanes of a wave merge lower group with upper
+            // group (both lanes of a pair compute the same merge), thread 0
+            // the waves in order; then the largest deviation from the mean
+            // from each chunk's minimum and maximum
+            __shared__ double sm[3 * (BLOCK / WAVE)];
+            const int64_t base = d.base, base2 = A.descs[ds].slot_base[ST_SSQ];
+            const int32_t m = d.cnt, per = (m + BLOCK - 1) / BLOCK;
+            const int32_t k0 = min(m, tid * per), k1 = min(m, k0 + per);
+            double cn = 0.0, cm = 0.0, c2 = 0.0;
+            for (int32_t k = k0; k < k1; ++k) {
+                const Slot sl = A.slots[base + k];
+                const double nk = (double)min((int64_t)d.chunk, d.n - (int64_t)k * d.chunk);
+                chan_merge(cn, cm, c2, nk, sl.v / nk, sl.aux);
+            }
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int32_t k = k0 + u * BLOCK;
-                    buf[u] = k < n_slots ? A.slots[base + k].v : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const double tt = s + buf[u];
-                    c += fabs(s) >= fabs(buf[u]) ? (s - tt) + buf[u] : (buf[u] - tt) + s;
-                    s = tt;
+            for (int off = 1; off < WAVE; off <<= 1) {
+                const double on = __shfl_xor(cn, off, WAVE), om = __shfl_xor(cm, off, WAVE);
+                const double o2 = __shfl_xor(c2, off, WAVE);
+                if (tid & off) {
+                    double ln = on, lm = om, l2 = o2;
+                    chan_merge(ln, lm, l2, cn, cm, c2);
+                    cn = ln;
+                    cm = lm;
+                    c2 = l2;
+                } else {
+                    chan_merge(cn, cm, c2, on, om, o2);
                 }
             }
-            if (stage == ST_SSQ)
-                for (int32_t k = tid; k < n_slots; k += BLOCK) m = fmax(m, A.slots[base + k].aux);
-            tot = block_sum<BLOCK>(s + c, red);
-            mx = block_max<BLOCK>(m, red);
+            if ((tid & (WAVE - 1)) == 0) {
+                sm[3 * (tid / WAVE)] = cn;
+                sm[3 * (tid / WAVE) + 1] = cm;
+                sm[3 * (tid / WAVE) + 2] = c2;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double N = 0.0, M = 0.0, Q = 0.0;
+                for (int w = 0; w < BLOCK / WAVE; ++w) chan_merge(N, M, Q, sm[3 * w], sm[3 * w + 1], sm[3 * w + 2]);
+                sm[0] = load_x(d.x, d.dtype, 0) + M;  // the chunks' sums were taken about x[0]
+                sm[1] = Q;
+            }
+            __syncthreads();
+            mean = sm[0];
+            tot = sm[1];
+            double dm = 0.0;
+            for (int32_t k = k0; k < k1; ++k) {
+                const Slot sl = A.slots[base2 + k];
+                dm = fmax(dm, fmax(sl.aux - mean, mean - sl.v));
+            }
+            mx = block_max<BLOCK>(dm, red);
         }
         if (tid == 0) {
+            int32_t flag = stage;
             if (stage >= ST_PSI6) tot = fx_value(a);
-            *pub = finalize_stage<PREC>(d, st, stage, tot, mx, pr, A.pc);
-            __hip_atomic_store(&st->t_fin[stage], (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            st_release(&st->ready[stage], 1u);
+            if (stage == ST_SUM) {
+                // mean, then sigma and Steps II-III as the second stage's finaliser
+                if (!(isfinite(mean) && isfinite(tot))) {
+                    set_status(st, KDE_ENONFINITE);
+                    pr.status = KDE_ENONFINITE;
+                }
+                st_f64(&st->mean, mean);
+                pr.mean = mean;
+                *pub = finalize_stage<PREC>(d, st, ST_SSQ, tot, mx, pr, A.pc);
+                flag = ST_SSQ;
+                const uint64_t now = wall_clock64();
+                __hip_atomic_store(&st->t_fin[ST_SUM], now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&st->t_fin[ST_SSQ], now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st_release(&st->ready[ST_SUM], 1u);
+            } else {
+                *pub = finalize_stage<PREC>(d, st, stage, tot, mx, pr, A.pc);
+                __hip_atomic_store(&st->t_fin[stage], (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            st_release(&st->ready[flag], 1u);
         }
         __syncthreads();
         if (tid < kPubReplicas) {
-            // every replica gets the values, then its flag with release order
+            // every replica gets the values, then its flag(s) with release order
             Pub* q = A.pubs + (int64_t)ds * kPubReplicas + tid;
             __hip_atomic_store(&q->status, pub->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&q->safe, pub->safe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             st_f64(&q->mean, pub->mean);
             st_f64(&q->scale, pub->scale);
-            st_release(&q->ready[stage], 1u);
+            if (stage == ST_SUM) st_release(&q->ready[ST_SUM], 1u);
+            st_release(&q->ready[stage == ST_SUM ? ST_SSQ : stage], 1u);
         }
     }
     __syncthreads();
@@ -1211,7 +1304,7 @@ __device__ void complete_items(const LaunchArgs& A, int32_t ds, const View& d, S
 // has counted everything: every stage counter reaches its item count and
 // every flag is published.
 template <int PREC, int R, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_persistent(LaunchArgs A) {
     using TileT = typename std::conditional<PREC >= 1 && PREC <= 3, float, double>::type;
     __shared__ __align__(16) TileT tile[TJ];
     __shared__ double red[BLOCK / WAVE];
@@ -1304,16 +1397,23 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
         const double mean = sh_mean, scale = sh_scale;
         const int32_t safe = sh_safe;
 
-        double v = 0.0, aux = 0.0;
+        double v = 0.0;
         q32 vq = 0;  // Q32.32 item sum (fixed-point mode)
         if (status == 0) {
             switch (it.stage) {
-            case ST_SUM:
-                v = moment_sum<BLOCK>(d, it.a, red);
+            case ST_SUM: {
+                // the chunk's (sum, squared deviations) in its own slot, its
+                // (min, max) in the slot of the same chunk in the second stage
+                double sum, m2, lo, hi;
+                moment_stats<BLOCK>(d, it.a, red, &sum, &m2, &lo, &hi);
+                if (tid == 0) {
+                    A.slots[it.slot] = Slot{sum, m2};
+                    A.slots[A.descs[it.ds].slot_base[ST_SSQ] + it.a] = Slot{lo, hi};
+                }
                 break;
+            }
             case ST_SSQ:
-                moment_ssq<BLOCK>(d, it.a, mean, red, &v, &aux);
-                break;
+                break;  // Step I's first finaliser has done this stage's work
             case ST_PSI6:
             case ST_PSI4:
                 if constexpr (PREC == 4) {
@@ -1354,11 +1454,6 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(LaunchArgs A) {
                     fx_add(pacc, v);
                 else if (status == 0)
                     set_status(st, KDE_EDEGENERATE);  // non-finite or out of range partial
-            } else {
-                Slot s;
-                s.v = v;
-                s.aux = aux;
-                A.slots[it.slot] = s;
             }
             next = atomicAdd(A.ticket, 1u);
             sh_flush = next >= (uint32_t)it.run_end ? 1 : 0;

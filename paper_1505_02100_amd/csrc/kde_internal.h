@@ -116,8 +116,8 @@ static_assert(sizeof(Pub) == 128, "Pub layout");
 
 // Partial result of one work item.
 struct Slot {
-    double v;    // sum
-    double aux;  // moments pass 2: max |x - mean|; otherwise 0
+    double v;    // Step I chunk: its sum of x - x[0] (first stage's slot) or its minimum (second stage's)
+    double aux;  // its squared deviations from its own mean (first) or its maximum (second)
 };
 
 // Constants of the FP32 pair evaluation (derivation in kde_device.hip).

@@ -278,6 +278,20 @@ def test_batch_matches_oracle(ctx64, ctx32):
         _check(b, ref, TOL32_H, TOL32_PSI)
 
 
+@pytest.mark.parametrize("n,offset", [(300_001, 1e6), (1_000_003, -3e4)])
+def test_step1_many_chunks_far_from_origin(ctx64, ctx32, n, offset):
+    # Step I merges many chunks (the last one ragged) of a sample whose mean
+    # is far from 0 in units of its spread; every precision runs the same
+    # FP64 Step I, so mean and sigma agree bitwise across precisions
+    x = offset + 3.0 * synth.normal(n, 77)
+    m, s = oracle.moments(x)
+    r64 = ctx64.plugin_bandwidth(x)
+    r32 = ctx32.plugin_bandwidth(x)
+    assert r64.status == 0 and r32.status == 0
+    assert _rel(r64.mean, m) < 1e-14 and _rel(r64.sigma, s) < 1e-12, (r64.mean, m, r64.sigma, s)
+    assert (r32.mean, r32.sigma, r32.g1) == (r64.mean, r64.sigma, r64.g1)
+
+
 def test_deterministic_repeat(ctx32):
     x = synth.bimodal(12345, 5)
     a = ctx32.plugin_bandwidth(x)
