@@ -662,6 +662,344 @@ __device__ __forceinline__ void pair16_loop_r6_f32(uint32_t addr, int32_t cnt, f
         : "v80", "v81", "v82", "v83", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101", "v125", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "v144", "v145", "v146", "v147", "v148", "v149", "v150", "v151", "v152", "v153", "v154", "v155", "v156", "v157", "scc", "memory");
 }
 
+// The exact-k variant (KDE_FP32_KAHAN_EXACT) of the Step IV loop above:
+// per pair d = ui - xj, Y = d d, a = fma(Y, k_hi, Y k_lo), e = 2^(-a),
+// p = ((Y - 15) Y + 45) Y - 15, column c into accumulator c, the same fold.
+// The compiler's own code for the step, registers included, written out
+// whole for the same reason: left to the compiler, its schedule moved with
+// unrelated changes to the kernel and ran 20% slower.
+__device__ __forceinline__ void pair16_loop_r6x_f32(uint32_t addr, int32_t cnt, float ui, float khi, float klo,
+                                                 double& tot) {
+    asm volatile(
+        ".p2align 6\n"
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "1:\n"
+        "v_mov_b32_e32 v83, %[addr]\n"
+        "ds_read_b128 v[78:81], v83\n"
+        "ds_read_b128 v[84:87], v83 offset:16\n"
+        "ds_read_b128 v[88:91], v83 offset:32\n"
+        "ds_read_b128 v[92:95], v83 offset:48\n"
+        "s_add_u32 %[addr], %[addr], 64\n"
+        "s_waitcnt lgkmcnt(0)\n"
+        "v_sub_f32_e32 v78, %[ui], v78\n"
+        "v_sub_f32_e32 v79, %[ui], v79\n"
+        "v_sub_f32_e32 v80, %[ui], v80\n"
+        "v_sub_f32_e32 v81, %[ui], v81\n"
+        "v_sub_f32_e32 v83, %[ui], v84\n"
+        "v_sub_f32_e32 v84, %[ui], v85\n"
+        "v_sub_f32_e32 v85, %[ui], v86\n"
+        "v_sub_f32_e32 v86, %[ui], v87\n"
+        "v_sub_f32_e32 v87, %[ui], v88\n"
+        "v_sub_f32_e32 v88, %[ui], v89\n"
+        "v_sub_f32_e32 v89, %[ui], v90\n"
+        "v_sub_f32_e32 v90, %[ui], v91\n"
+        "v_sub_f32_e32 v91, %[ui], v92\n"
+        "v_sub_f32_e32 v92, %[ui], v93\n"
+        "v_sub_f32_e32 v93, %[ui], v94\n"
+        "v_sub_f32_e32 v94, %[ui], v95\n"
+        "v_mul_f32_e32 v95, v78, v78\n"
+        "v_mul_f32_e32 v96, v79, v79\n"
+        "v_mul_f32_e32 v97, v80, v80\n"
+        "v_mul_f32_e32 v98, v81, v81\n"
+        "v_fmaak_f32 v78, v78, v78, 0xc1700000\n"
+        "v_fmaak_f32 v79, v79, v79, 0xc1700000\n"
+        "v_fmaak_f32 v80, v80, v80, 0xc1700000\n"
+        "v_fmaak_f32 v81, v81, v81, 0xc1700000\n"
+        "v_mul_f32_e32 v99, v83, v83\n"
+        "v_mul_f32_e32 v123, v84, v84\n"
+        "v_mul_f32_e32 v130, v85, v85\n"
+        "v_mul_f32_e32 v131, v86, v86\n"
+        "v_mul_f32_e32 v140, %[klo], v95\n"
+        "v_mul_f32_e32 v141, %[klo], v96\n"
+        "v_mul_f32_e32 v142, %[klo], v97\n"
+        "v_mul_f32_e32 v143, %[klo], v98\n"
+        "v_fmaak_f32 v83, v83, v83, 0xc1700000\n"
+        "v_fmaak_f32 v84, v84, v84, 0xc1700000\n"
+        "v_fmaak_f32 v85, v85, v85, 0xc1700000\n"
+        "v_fmaak_f32 v86, v86, v86, 0xc1700000\n"
+        "v_mul_f32_e32 v132, v87, v87\n"
+        "v_mul_f32_e32 v133, v88, v88\n"
+        "v_mul_f32_e32 v134, v89, v89\n"
+        "v_mul_f32_e32 v135, v90, v90\n"
+        "v_fmaak_f32 v78, v78, v95, 0x42340000\n"
+        "v_fmaak_f32 v79, v79, v96, 0x42340000\n"
+        "v_fmaak_f32 v80, v80, v97, 0x42340000\n"
+        "v_fmaak_f32 v81, v81, v98, 0x42340000\n"
+        "v_mul_f32_e32 v144, %[klo], v99\n"
+        "v_mul_f32_e32 v145, %[klo], v123\n"
+        "v_mul_f32_e32 v146, %[klo], v130\n"
+        "v_mul_f32_e32 v147, %[klo], v131\n"
+        "v_fmac_f32_e32 v140, %[khi], v95\n"
+        "v_fmac_f32_e32 v141, %[khi], v96\n"
+        "v_fmac_f32_e32 v142, %[khi], v97\n"
+        "v_fmac_f32_e32 v143, %[khi], v98\n"
+        "v_fmaak_f32 v87, v87, v87, 0xc1700000\n"
+        "v_fmaak_f32 v88, v88, v88, 0xc1700000\n"
+        "v_fmaak_f32 v89, v89, v89, 0xc1700000\n"
+        "v_fmaak_f32 v90, v90, v90, 0xc1700000\n"
+        "v_mul_f32_e32 v136, v91, v91\n"
+        "v_mul_f32_e32 v137, v92, v92\n"
+        "v_mul_f32_e32 v138, v93, v93\n"
+        "v_mul_f32_e32 v139, v94, v94\n"
+        "v_fmaak_f32 v83, v83, v99, 0x42340000\n"
+        "v_fmaak_f32 v84, v84, v123, 0x42340000\n"
+        "v_fmaak_f32 v85, v85, v130, 0x42340000\n"
+        "v_fmaak_f32 v86, v86, v131, 0x42340000\n"
+        "v_mul_f32_e32 v148, %[klo], v132\n"
+        "v_mul_f32_e32 v149, %[klo], v133\n"
+        "v_mul_f32_e32 v150, %[klo], v134\n"
+        "v_mul_f32_e32 v151, %[klo], v135\n"
+        "v_fmaak_f32 v78, v78, v95, 0xc1700000\n"
+        "v_fmaak_f32 v79, v79, v96, 0xc1700000\n"
+        "v_fmaak_f32 v80, v80, v97, 0xc1700000\n"
+        "v_fmaak_f32 v81, v81, v98, 0xc1700000\n"
+        "v_fmac_f32_e32 v144, %[khi], v99\n"
+        "v_fmac_f32_e32 v145, %[khi], v123\n"
+        "v_fmac_f32_e32 v146, %[khi], v130\n"
+        "v_fmac_f32_e32 v147, %[khi], v131\n"
+        "v_exp_f32_e64 v95, -v140\n"
+        "v_exp_f32_e64 v96, -v141\n"
+        "v_exp_f32_e64 v97, -v142\n"
+        "v_exp_f32_e64 v98, -v143\n"
+        "v_fmaak_f32 v91, v91, v91, 0xc1700000\n"
+        "v_fmaak_f32 v92, v92, v92, 0xc1700000\n"
+        "v_fmaak_f32 v93, v93, v93, 0xc1700000\n"
+        "v_fmaak_f32 v94, v94, v94, 0xc1700000\n"
+        "v_fmaak_f32 v87, v87, v132, 0x42340000\n"
+        "v_fmaak_f32 v88, v88, v133, 0x42340000\n"
+        "v_fmaak_f32 v89, v89, v134, 0x42340000\n"
+        "v_fmaak_f32 v90, v90, v135, 0x42340000\n"
+        "v_mul_f32_e32 v152, %[klo], v136\n"
+        "v_mul_f32_e32 v153, %[klo], v137\n"
+        "v_mul_f32_e32 v154, %[klo], v138\n"
+        "v_mul_f32_e32 v155, %[klo], v139\n"
+        "v_fmaak_f32 v83, v83, v99, 0xc1700000\n"
+        "v_fmaak_f32 v84, v84, v123, 0xc1700000\n"
+        "v_fmaak_f32 v85, v85, v130, 0xc1700000\n"
+        "v_fmaak_f32 v86, v86, v131, 0xc1700000\n"
+        "v_fmac_f32_e32 v148, %[khi], v132\n"
+        "v_fmac_f32_e32 v149, %[khi], v133\n"
+        "v_fmac_f32_e32 v150, %[khi], v134\n"
+        "v_fmac_f32_e32 v151, %[khi], v135\n"
+        "v_exp_f32_e64 v99, -v144\n"
+        "v_exp_f32_e64 v123, -v145\n"
+        "v_exp_f32_e64 v130, -v146\n"
+        "v_exp_f32_e64 v131, -v147\n"
+        "v_fmaak_f32 v91, v91, v136, 0x42340000\n"
+        "v_fmaak_f32 v92, v92, v137, 0x42340000\n"
+        "v_fmaak_f32 v93, v93, v138, 0x42340000\n"
+        "v_fmaak_f32 v94, v94, v139, 0x42340000\n"
+        "v_fmaak_f32 v87, v87, v132, 0xc1700000\n"
+        "v_fmaak_f32 v88, v88, v133, 0xc1700000\n"
+        "v_fmaak_f32 v89, v89, v134, 0xc1700000\n"
+        "v_fmaak_f32 v90, v90, v135, 0xc1700000\n"
+        "v_fmac_f32_e32 v152, %[khi], v136\n"
+        "v_fmac_f32_e32 v153, %[khi], v137\n"
+        "v_fmac_f32_e32 v154, %[khi], v138\n"
+        "v_fmac_f32_e32 v155, %[khi], v139\n"
+        "v_exp_f32_e64 v132, -v148\n"
+        "v_exp_f32_e64 v133, -v149\n"
+        "v_exp_f32_e64 v134, -v150\n"
+        "v_exp_f32_e64 v135, -v151\n"
+        "v_fmaak_f32 v91, v91, v136, 0xc1700000\n"
+        "v_fmaak_f32 v92, v92, v137, 0xc1700000\n"
+        "v_fmaak_f32 v93, v93, v138, 0xc1700000\n"
+        "v_fmaak_f32 v94, v94, v139, 0xc1700000\n"
+        "v_exp_f32_e64 v136, -v152\n"
+        "v_exp_f32_e64 v137, -v153\n"
+        "v_exp_f32_e64 v138, -v154\n"
+        "v_exp_f32_e64 v139, -v155\n"
+        "v_fma_f32 v78, v78, v95, 0\n"
+        "v_fma_f32 v79, v79, v96, 0\n"
+        "v_fma_f32 v80, v80, v97, 0\n"
+        "v_fma_f32 v81, v81, v98, 0\n"
+        "v_fmac_f32_e32 v78, v83, v99\n"
+        "v_fmac_f32_e32 v79, v84, v123\n"
+        "v_fmac_f32_e32 v80, v85, v130\n"
+        "v_fmac_f32_e32 v81, v86, v131\n"
+        "v_fmac_f32_e32 v78, v87, v132\n"
+        "v_fmac_f32_e32 v79, v88, v133\n"
+        "v_fmac_f32_e32 v80, v89, v134\n"
+        "v_fmac_f32_e32 v81, v90, v135\n"
+        "v_fmac_f32_e32 v78, v91, v136\n"
+        "v_fmac_f32_e32 v79, v92, v137\n"
+        "v_fmac_f32_e32 v80, v93, v138\n"
+        "v_fmac_f32_e32 v81, v94, v139\n"
+        "v_add_f32_e32 v78, v78, v79\n"
+        "v_add_f32_e32 v79, v80, v81\n"
+        "s_sub_u32 %[cnt], %[cnt], 1\n"
+        "v_add_f32_e32 v78, v78, v79\n"
+        "v_cvt_f64_f32_e32 v[78:79], v78\n"
+        "s_cmp_lg_u32 %[cnt], 0\n"
+        "v_add_f64 %[tot], %[tot], v[78:79]\n"
+        "s_cbranch_scc1 1b\n"
+        : [tot] "+{v[72:73]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
+        : [ui] "{v82}"(ui), [khi] "s"(khi), [klo] "s"(klo)
+        : "v78", "v79", "v80", "v81", "v83", "v84", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v123", "v130", "v131", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "v144", "v145", "v146", "v147", "v148", "v149", "v150", "v151", "v152", "v153", "v154", "v155", "scc", "memory");
+}
+
+// The exact-k variant of the Step VI loop: as above with
+// p = (Y - 6) Y + 3.
+__device__ __forceinline__ void pair16_loop_r4x_f32(uint32_t addr, int32_t cnt, float ui, float khi, float klo,
+                                                 double& tot) {
+    asm volatile(
+        ".p2align 6\n"
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "s_nop 0\n"
+        "1:\n"
+        "v_mov_b32_e32 v83, %[addr]\n"
+        "ds_read_b128 v[78:81], v83\n"
+        "ds_read_b128 v[84:87], v83 offset:16\n"
+        "ds_read_b128 v[88:91], v83 offset:32\n"
+        "ds_read_b128 v[92:95], v83 offset:48\n"
+        "s_add_u32 %[addr], %[addr], 64\n"
+        "s_waitcnt lgkmcnt(0)\n"
+        "v_sub_f32_e32 v78, %[ui], v78\n"
+        "v_sub_f32_e32 v79, %[ui], v79\n"
+        "v_sub_f32_e32 v80, %[ui], v80\n"
+        "v_sub_f32_e32 v81, %[ui], v81\n"
+        "v_sub_f32_e32 v83, %[ui], v84\n"
+        "v_sub_f32_e32 v84, %[ui], v85\n"
+        "v_sub_f32_e32 v85, %[ui], v86\n"
+        "v_sub_f32_e32 v86, %[ui], v87\n"
+        "v_sub_f32_e32 v87, %[ui], v88\n"
+        "v_sub_f32_e32 v88, %[ui], v89\n"
+        "v_sub_f32_e32 v89, %[ui], v90\n"
+        "v_sub_f32_e32 v90, %[ui], v91\n"
+        "v_sub_f32_e32 v91, %[ui], v92\n"
+        "v_sub_f32_e32 v92, %[ui], v93\n"
+        "v_sub_f32_e32 v93, %[ui], v94\n"
+        "v_sub_f32_e32 v94, %[ui], v95\n"
+        "v_mul_f32_e32 v95, v78, v78\n"
+        "v_mul_f32_e32 v96, v79, v79\n"
+        "v_mul_f32_e32 v97, v80, v80\n"
+        "v_mul_f32_e32 v98, v81, v81\n"
+        "v_mul_f32_e32 v99, v83, v83\n"
+        "v_mul_f32_e32 v123, v84, v84\n"
+        "v_mul_f32_e32 v130, v85, v85\n"
+        "v_mul_f32_e32 v131, v86, v86\n"
+        "v_mul_f32_e32 v140, %[klo], v95\n"
+        "v_mul_f32_e32 v141, %[klo], v96\n"
+        "v_mul_f32_e32 v142, %[klo], v97\n"
+        "v_mul_f32_e32 v143, %[klo], v98\n"
+        "v_fmaak_f32 v78, v78, v78, 0xc0c00000\n"
+        "v_fmaak_f32 v79, v79, v79, 0xc0c00000\n"
+        "v_fmaak_f32 v80, v80, v80, 0xc0c00000\n"
+        "v_fmaak_f32 v81, v81, v81, 0xc0c00000\n"
+        "v_mul_f32_e32 v132, v87, v87\n"
+        "v_mul_f32_e32 v133, v88, v88\n"
+        "v_mul_f32_e32 v134, v89, v89\n"
+        "v_mul_f32_e32 v135, v90, v90\n"
+        "v_mul_f32_e32 v144, %[klo], v99\n"
+        "v_mul_f32_e32 v145, %[klo], v123\n"
+        "v_mul_f32_e32 v146, %[klo], v130\n"
+        "v_mul_f32_e32 v147, %[klo], v131\n"
+        "v_fmac_f32_e32 v140, %[khi], v95\n"
+        "v_fmac_f32_e32 v141, %[khi], v96\n"
+        "v_fmac_f32_e32 v142, %[khi], v97\n"
+        "v_fmac_f32_e32 v143, %[khi], v98\n"
+        "v_fmaak_f32 v83, v83, v83, 0xc0c00000\n"
+        "v_fmaak_f32 v84, v84, v84, 0xc0c00000\n"
+        "v_fmaak_f32 v85, v85, v85, 0xc0c00000\n"
+        "v_fmaak_f32 v86, v86, v86, 0xc0c00000\n"
+        "v_mul_f32_e32 v136, v91, v91\n"
+        "v_mul_f32_e32 v137, v92, v92\n"
+        "v_mul_f32_e32 v138, v93, v93\n"
+        "v_mul_f32_e32 v139, v94, v94\n"
+        "v_fmaak_f32 v78, v78, v95, 0x40400000\n"
+        "v_fmaak_f32 v79, v79, v96, 0x40400000\n"
+        "v_fmaak_f32 v80, v80, v97, 0x40400000\n"
+        "v_fmaak_f32 v81, v81, v98, 0x40400000\n"
+        "v_mul_f32_e32 v148, %[klo], v132\n"
+        "v_mul_f32_e32 v149, %[klo], v133\n"
+        "v_mul_f32_e32 v150, %[klo], v134\n"
+        "v_mul_f32_e32 v151, %[klo], v135\n"
+        "v_fmac_f32_e32 v144, %[khi], v99\n"
+        "v_fmac_f32_e32 v145, %[khi], v123\n"
+        "v_fmac_f32_e32 v146, %[khi], v130\n"
+        "v_fmac_f32_e32 v147, %[khi], v131\n"
+        "v_exp_f32_e64 v95, -v140\n"
+        "v_exp_f32_e64 v96, -v141\n"
+        "v_exp_f32_e64 v97, -v142\n"
+        "v_exp_f32_e64 v98, -v143\n"
+        "v_fmaak_f32 v87, v87, v87, 0xc0c00000\n"
+        "v_fmaak_f32 v88, v88, v88, 0xc0c00000\n"
+        "v_fmaak_f32 v89, v89, v89, 0xc0c00000\n"
+        "v_fmaak_f32 v90, v90, v90, 0xc0c00000\n"
+        "v_fmaak_f32 v83, v83, v99, 0x40400000\n"
+        "v_fmaak_f32 v84, v84, v123, 0x40400000\n"
+        "v_fmaak_f32 v85, v85, v130, 0x40400000\n"
+        "v_fmaak_f32 v86, v86, v131, 0x40400000\n"
+        "v_mul_f32_e32 v152, %[klo], v136\n"
+        "v_mul_f32_e32 v153, %[klo], v137\n"
+        "v_mul_f32_e32 v154, %[klo], v138\n"
+        "v_mul_f32_e32 v155, %[klo], v139\n"
+        "v_fmac_f32_e32 v148, %[khi], v132\n"
+        "v_fmac_f32_e32 v149, %[khi], v133\n"
+        "v_fmac_f32_e32 v150, %[khi], v134\n"
+        "v_fmac_f32_e32 v151, %[khi], v135\n"
+        "v_exp_f32_e64 v99, -v144\n"
+        "v_exp_f32_e64 v123, -v145\n"
+        "v_exp_f32_e64 v130, -v146\n"
+        "v_exp_f32_e64 v131, -v147\n"
+        "v_fmaak_f32 v91, v91, v91, 0xc0c00000\n"
+        "v_fmaak_f32 v92, v92, v92, 0xc0c00000\n"
+        "v_fmaak_f32 v93, v93, v93, 0xc0c00000\n"
+        "v_fmaak_f32 v94, v94, v94, 0xc0c00000\n"
+        "v_fmaak_f32 v87, v87, v132, 0x40400000\n"
+        "v_fmaak_f32 v88, v88, v133, 0x40400000\n"
+        "v_fmaak_f32 v89, v89, v134, 0x40400000\n"
+        "v_fmaak_f32 v90, v90, v135, 0x40400000\n"
+        "v_fmac_f32_e32 v152, %[khi], v136\n"
+        "v_fmac_f32_e32 v153, %[khi], v137\n"
+        "v_fmac_f32_e32 v154, %[khi], v138\n"
+        "v_fmac_f32_e32 v155, %[khi], v139\n"
+        "v_exp_f32_e64 v132, -v148\n"
+        "v_exp_f32_e64 v133, -v149\n"
+        "v_exp_f32_e64 v134, -v150\n"
+        "v_exp_f32_e64 v135, -v151\n"
+        "v_fmaak_f32 v91, v91, v136, 0x40400000\n"
+        "v_fmaak_f32 v92, v92, v137, 0x40400000\n"
+        "v_fmaak_f32 v93, v93, v138, 0x40400000\n"
+        "v_fmaak_f32 v94, v94, v139, 0x40400000\n"
+        "v_exp_f32_e64 v136, -v152\n"
+        "v_exp_f32_e64 v137, -v153\n"
+        "v_exp_f32_e64 v138, -v154\n"
+        "v_exp_f32_e64 v139, -v155\n"
+        "v_fma_f32 v78, v78, v95, 0\n"
+        "v_fma_f32 v79, v79, v96, 0\n"
+        "v_fma_f32 v80, v80, v97, 0\n"
+        "v_fma_f32 v81, v81, v98, 0\n"
+        "v_fmac_f32_e32 v78, v83, v99\n"
+        "v_fmac_f32_e32 v79, v84, v123\n"
+        "v_fmac_f32_e32 v80, v85, v130\n"
+        "v_fmac_f32_e32 v81, v86, v131\n"
+        "v_fmac_f32_e32 v78, v87, v132\n"
+        "v_fmac_f32_e32 v79, v88, v133\n"
+        "v_fmac_f32_e32 v80, v89, v134\n"
+        "v_fmac_f32_e32 v81, v90, v135\n"
+        "v_fmac_f32_e32 v78, v91, v136\n"
+        "v_fmac_f32_e32 v79, v92, v137\n"
+        "v_fmac_f32_e32 v80, v93, v138\n"
+        "v_fmac_f32_e32 v81, v94, v139\n"
+        "v_add_f32_e32 v78, v78, v79\n"
+        "v_add_f32_e32 v79, v80, v81\n"
+        "s_sub_u32 %[cnt], %[cnt], 1\n"
+        "v_add_f32_e32 v78, v78, v79\n"
+        "v_cvt_f64_f32_e32 v[78:79], v78\n"
+        "s_cmp_lg_u32 %[cnt], 0\n"
+        "v_add_f64 %[tot], %[tot], v[78:79]\n"
+        "s_cbranch_scc1 1b\n"
+        : [tot] "+{v[72:73]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
+        : [ui] "{v82}"(ui), [khi] "s"(khi), [klo] "s"(klo)
+        : "v78", "v79", "v80", "v81", "v83", "v84", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v123", "v130", "v131", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "v144", "v145", "v146", "v147", "v148", "v149", "v150", "v151", "v152", "v153", "v154", "v155", "scc", "memory");
+}
+
 // Columns [c0, c1) of pair item cb of the row block starting at row r0
 // (row_chunks gives the chunk width; the host enumerates items with it).
 __device__ __forceinline__ void item_columns(int64_t n, int64_t r0, int64_t W, int32_t cb,
@@ -763,6 +1101,14 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
                     const uint32_t lds = (uint32_t)(size_t)((__attribute__((address_space(3))) float*)tile) + 4u * (uint32_t)jj;
                     if constexpr (RO == 4) pair16_loop_r4_f32(lds, groups, ui[0], pc.k_hi, tot[0]);
                     else pair16_loop_r6_f32(lds, groups, ui[0], pc.k_hi, tot[0]);
+                    jj += groups << 4;
+                }
+            } else if constexpr ((RO == 4 || RO == 6) && R == 1 && !SAFE && EXACT_K && !PEXP && kFold == 4) {
+                const int32_t groups = (len - jj) >> 4;
+                if (groups > 0) {
+                    const uint32_t lds = (uint32_t)(size_t)((__attribute__((address_space(3))) float*)tile) + 4u * (uint32_t)jj;
+                    if constexpr (RO == 4) pair16_loop_r4x_f32(lds, groups, ui[0], pc.k_hi, pc.k_lo, tot[0]);
+                    else pair16_loop_r6x_f32(lds, groups, ui[0], pc.k_hi, pc.k_lo, tot[0]);
                     jj += groups << 4;
                 }
             } else {

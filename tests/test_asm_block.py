@@ -1,6 +1,7 @@
-"""The fixed-order loops of Steps IV and VI (`pair16_loop_r6_f32` and
-`pair16_loop_r4_f32` in kde_device.hip) read back from the source and executed
-instruction by instruction on the CPU.
+"""The asm loops of Steps IV and VI (`pair16_loop_r6_f32`, `pair16_loop_r4_f32`
+and their exact-k variants `pair16_loop_r6x_f32`, `pair16_loop_r4x_f32` in
+kde_device.hip) read back from the source and executed instruction by
+instruction on the CPU.
 
 Each loop runs the 16-column step of its stage, written out as gfx950 assembly
 (equations (6)-(7) with the Gaussian kernel's sixth and fourth derivatives,
@@ -62,11 +63,11 @@ def literal(tok):
     return f32(float(tok))
 
 
-def execute(lines, x, ui, k, tot, cnt=None):
+def execute(lines, x, ui, k, tot, cnt=None, k_lo=0.0):
     """Run a block on one lane.  x is the LDS tile (FP32 values from byte
     address 0); a whole-loop block runs cnt groups of 16 columns from there."""
     reg = {f"x{j}": f32(x[j]) for j in range(min(16, len(x)))}
-    reg.update(ui=f32(ui), k=f32(k), tot=float(tot), addr=0, cnt=cnt, scc=0)
+    reg.update(ui=f32(ui), k=f32(k), khi=f32(k), klo=f32(k_lo), tot=float(tot), addr=0, cnt=cnt, scc=0)
     labels = {l[:-1]: i for i, l in enumerate(lines) if l.endswith(":")}
 
     def val(tok):
@@ -154,14 +155,55 @@ def step_iv_reference(x, ui, k, tot):
     return float(tot) + float(f32(f32(acc[0] + acc[1]) + f32(acc[2] + acc[3])))
 
 
+def exact_k_reference(r):
+    def ref(x, ui, k, tot, k_lo):
+        acc = [None] * 4
+        for j in range(16):
+            d = f32(f32(ui) - f32(x[j]))
+            y = f32(d * d)
+            a = fma32(y, f32(k), f32(y * f32(k_lo)))
+            e = exp2_32(f32(-a))
+            # Y - c is contracted with the product: fma(d, d, -c)
+            if r == 6:
+                q = fma32(d, d, f32(-15.0))
+                q = fma32(q, y, f32(45.0))
+                p = fma32(q, y, f32(-15.0))
+            else:
+                q = fma32(d, d, f32(-6.0))
+                p = fma32(q, y, f32(3.0))
+            c = j % 4
+            acc[c] = fma32(p, e, f32(0.0)) if acc[c] is None else fma32(p, e, acc[c])
+        return float(tot) + float(f32(f32(acc[0] + acc[1]) + f32(acc[2] + acc[3])))
+    return ref
+
+
 R6, R4 = "pair16_loop_r6_f32", "pair16_loop_r4_f32"
+R6X, R4X = "pair16_loop_r6x_f32", "pair16_loop_r4x_f32"
 K = f32(np.log2(np.e) / 2)
+K_LO = f32(np.log2(np.e) / 2 - float(K))
 
 
 def run_groups(ref, x, ui, k, tot, cnt):
     for g in range(cnt):
         tot = ref(x[16 * g:16 * g + 16], ui, k, tot)
     return tot
+
+
+@pytest.mark.parametrize("name,r,seed", [(R6X, 6, 9), (R4X, 4, 11)])
+def test_exact_k_loop_computes_the_pair_terms(name, r, seed):
+    lines = block_lines(name)
+    assert sum(l.startswith("v_exp_f32") for l in lines) == 16
+    ref = exact_k_reference(r)
+    rng = np.random.default_rng(seed)
+    for trial in range(60):
+        cnt = 1 + trial % 3
+        x = np.concatenate([rng.normal(0.0, 2.0, 16 * cnt), np.full(16, np.nan)]).astype(np.float32)
+        ui = f32(rng.normal(0.0, 2.0))
+        tot = rng.normal()
+        want = tot
+        for g in range(cnt):
+            want = ref(x[16 * g:16 * g + 16], ui, K, want, K_LO)
+        assert execute(lines, x, ui, K, tot, cnt, K_LO) == want
 
 
 @pytest.mark.parametrize("name,ref,seed", [(R6, step_iv_reference, 5), (R4, step_vi_reference, 7)])
@@ -194,7 +236,7 @@ def test_step_vi_loop_detects_a_planted_error():
     assert execute(wrong, x, f32(0.3), K, 0.0, 2) != ref
 
 
-@pytest.mark.parametrize("name", [R6, R4])
+@pytest.mark.parametrize("name", [R6, R4, R6X, R4X])
 def test_transcendental_results_are_not_read_in_the_next_instruction(name):
     lines = block_lines(name)
     body = [l for l in lines if not l.endswith(":") and not l.startswith(".")]
@@ -211,7 +253,7 @@ def test_transcendental_results_are_not_read_in_the_next_instruction(name):
 HEAD_BYTES = {"v_mov_b32_e32": 4, "ds_read_b128": 8, "s_add_u32": 4, "s_sub_u32": 4, "s_waitcnt": 4}
 
 
-@pytest.mark.parametrize("name,mod64", [(R6, 60), (R4, 0)])
+@pytest.mark.parametrize("name,mod64", [(R6, 60), (R4, 0), (R6X, 60), (R4X, 60)])
 def test_loop_body_placement(name, mod64):
     # the block starts on a 64-byte boundary; the padding before the loop
     # label runs once per call, and the first VALU op of the body lands where
@@ -231,7 +273,7 @@ def test_loop_body_placement(name, mod64):
     assert off % 64 == mod64
 
 
-@pytest.mark.parametrize("name", [R6, R4])
+@pytest.mark.parametrize("name", [R6, R4, R6X, R4X])
 def test_block_operands_are_declared(name):
     text = open(SRC).read()
     start = text.index(f"void {name}(")
