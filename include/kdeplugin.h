@@ -158,9 +158,10 @@ KDE_API double kde_ctx_last_device_ms(const kde_ctx* ctx);
 /* Device timeline of sample `sample` of the last synchronous call on this
  * context: ms[k] (k < KDE_NUM_STAGES; the caller provides that many) =
  * milliseconds from the start of the sample's first work item to the moment
- * stage k published its result (k = 0: mean, 1: sigma and g1 (Steps I-III),
- * 2: Psi6 and g2 (Steps IV-V), 3: Psi4 and h (Steps VI-VII)); -1 for a stage
- * that did not run.  From the GPU's 100 MHz clock. */
+ * stage k published its result (k = 0: mean, 1: sigma and g1 (Steps I-III;
+ * Step I takes one pass, so entries 0 and 1 are equal), 2: Psi6 and g2
+ * (Steps IV-V), 3: Psi4 and h (Steps VI-VII)); -1 for a stage that did not
+ * run.  From the GPU's 100 MHz clock. */
 #define KDE_NUM_STAGES 4
 KDE_API int kde_ctx_last_timeline(const kde_ctx* ctx, int64_t sample, double* ms);
 

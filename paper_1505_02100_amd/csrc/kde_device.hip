@@ -93,6 +93,9 @@ __device__ __forceinline__ uint32_t ld_acquire(const uint32_t* p) {
 __device__ __forceinline__ void st_release(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void st_relaxed(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ double ld_f64(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1602,13 +1605,15 @@ __device__ void complete_items(const LaunchArgs& A, int32_t ds, const View& d, S
                 const uint64_t now = wall_clock64();
                 __hip_atomic_store(&st->t_fin[ST_SUM], now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&st->t_fin[ST_SSQ], now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                st_release(&st->ready[ST_SUM], 1u);
+                st_relaxed(&st->ready[ST_SUM], 1u);
             } else {
                 *pub = finalize_stage<PREC>(d, st, stage, tot, mx, pr, A.pc);
                 __hip_atomic_store(&st->t_fin[stage], (uint64_t)wall_clock64(), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
-            st_release(&st->ready[flag], 1u);
+            // read by the host after the launch only; waiting blocks poll the
+            // replicas below, whose release orders everything written here
+            st_relaxed(&st->ready[flag], 1u);
         }
         __syncthreads();
         if (tid < kPubReplicas) {

@@ -292,6 +292,15 @@ def test_step1_many_chunks_far_from_origin(ctx64, ctx32, n, offset):
     assert (r32.mean, r32.sigma, r32.g1) == (r64.mean, r64.sigma, r64.g1)
 
 
+def test_stage_timeline(ctx32):
+    # Step I publishes its two stages at once; the pair stages follow in order,
+    # all inside the launch's device time
+    ctx32.plugin_bandwidth(synth.bimodal(20000, 3))
+    tl = ctx32.last_timeline(0)
+    assert len(tl) == 4 and tl[0] == tl[1]
+    assert 0.0 <= tl[1] <= tl[2] <= tl[3] <= ctx32.last_device_ms(), tl
+
+
 def test_deterministic_repeat(ctx32):
     x = synth.bimodal(12345, 5)
     a = ctx32.plugin_bandwidth(x)
