@@ -150,9 +150,9 @@ KDE_API int kde_ctx_config(const kde_ctx* ctx, int32_t* rows_per_lane, int32_t* 
                    int32_t* tile_rows, int32_t* blocks_per_cu);
 
 /* Device time in milliseconds of the last synchronous call's launch on this
- * context (init kernel, persistent kernel and the few-hundred-byte state
- * read-back, replayed as one graph), measured with HIP events recorded on
- * the caller's stream around the launch; -1 if none yet. */
+ * context (persistent kernel and the few-hundred-byte state read-back,
+ * replayed as one graph; the reset of the states for the next call follows
+ * it), measured with HIP events on the caller's stream; -1 if none yet. */
 KDE_API double kde_ctx_last_device_ms(const kde_ctx* ctx);
 
 /* Device timeline of sample `sample` of the last synchronous call on this

@@ -61,6 +61,7 @@ struct Plan {
     State* h_states = nullptr;        // pinned
     int64_t n_slots = 0;
     hipGraphExec_t exec = nullptr;
+    bool primed = false;              // states reset once before the first replay
     int grid = 0;
     ~Plan() {
         if (exec) (void)hipGraphExecDestroy(exec);
