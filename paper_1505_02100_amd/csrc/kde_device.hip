@@ -1133,7 +1133,7 @@ __device__ double pair_item_f32(const View& d, int32_t rb, int32_t cb, double me
     double lane_tot = 0.0;
 #pragma unroll
     for (int k = 0; k < R; ++k) lane_tot += tot[k];
-    return block_sum<BLOCK>(lane_tot, red);
+    return lane_tot;  // this lane's partial: the caller reduces over the block
 }
 
 // ---------------------------------------------------- FP64 pair evaluation
@@ -1749,6 +1749,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         const int32_t safe = sh_safe;
 
         double v = 0.0;
+        bool lane_partial = false;  // v holds this lane's part of an FP32 pair item
         q32 vq = 0;  // Q32.32 item sum (fixed-point mode)
         if (status == 0) {
             switch (it.stage) {
@@ -1784,6 +1785,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
                     else
                         v = safe ? pair_item_f32<4, true, XK, R, BLOCK, PX>(d, it.a, it.b, mean, scale, A.pc, tl, red)
                                  : pair_item_f32<4, false, XK, R, BLOCK, PX>(d, it.a, it.b, mean, scale, A.pc, tl, red);
+                    lane_partial = true;
                 } else {
                     double* tl = reinterpret_cast<double*>(tile);
                     if (it.stage == ST_PSI6)
@@ -1797,6 +1799,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             }
         }
 
+        // the next ticket's round trip overlaps the block reduction of an
+        // FP32 pair item
+        if (tid == 0) next = atomicAdd(A.ticket, 1u);
+        if (__builtin_amdgcn_readfirstlane(lane_partial)) v = block_sum<BLOCK>(v, red);
         if (tid == 0) {
             if (PREC == 4 && it.stage >= ST_PSI6) {
                 fx_add_q(pacc, vq);
@@ -1806,7 +1812,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
                 else if (status == 0)
                     set_status(st, KDE_EDEGENERATE);  // non-finite or out of range partial
             }
-            next = atomicAdd(A.ticket, 1u);
             sh_flush = next >= (uint32_t)it.run_end ? 1 : 0;
         }
         pend_ds = it.ds;
