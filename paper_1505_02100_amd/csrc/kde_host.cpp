@@ -405,14 +405,20 @@ int run_plan(kde_ctx* c, Plan& p, hipStream_t s) {
             return hip_fail(e, "graph capture of the persistent kernel");
         }
     }
+    if (!p.ev_reset) HIPCHK(hipEventCreateWithFlags(&p.ev_reset, hipEventDisableTiming));
     if (!p.primed) {
         HIPCHK(launch_init((State*)p.d_states.p, (Pub*)p.d_pubs.p, p.count, (uint32_t*)p.d_ticket.p, s));
         p.primed = true;
+    } else if (s != p.reset_stream) {
+        // the reset after the previous replay ran on another stream
+        HIPCHK(hipStreamWaitEvent(s, p.ev_reset, 0));
     }
     HIPCHK(hipEventRecord(c->ev0, s));
     HIPCHK(hipGraphLaunch(p.exec, s));
     HIPCHK(hipEventRecord(c->ev1, s));
     HIPCHK(launch_init((State*)p.d_states.p, (Pub*)p.d_pubs.p, p.count, (uint32_t*)p.d_ticket.p, s));
+    HIPCHK(hipEventRecord(p.ev_reset, s));
+    p.reset_stream = s;
     return KDE_OK;
 }
 

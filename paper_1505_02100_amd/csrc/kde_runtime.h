@@ -62,9 +62,12 @@ struct Plan {
     int64_t n_slots = 0;
     hipGraphExec_t exec = nullptr;
     bool primed = false;              // states reset once before the first replay
+    hipEvent_t ev_reset = nullptr;    // recorded after the reset that follows each replay
+    hipStream_t reset_stream = nullptr;  // the stream that reset was issued on
     int grid = 0;
     ~Plan() {
         if (exec) (void)hipGraphExecDestroy(exec);
+        if (ev_reset) (void)hipEventDestroy(ev_reset);
         if (h_states) (void)hipHostFree(h_states);
     }
     size_t device_bytes() const {

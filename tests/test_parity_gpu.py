@@ -347,6 +347,19 @@ def test_f32_input_and_device_tensors(ctx64, ctx32):
     _check(ctx64.plugin_bandwidth(torch.from_numpy(x32).cuda()), ref32, TOL64, TOL64)
 
 
+def test_calls_on_alternating_streams(ctx32):
+    # a plan's states are reset after each call on that call's stream; a call
+    # on another stream waits for that reset
+    import torch
+    xd = torch.from_numpy(synth.bimodal(30000, 29)).cuda()
+    ref = ctx32.plugin_bandwidth(xd)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for k in range(6):
+        with torch.cuda.stream(s1 if k % 2 == 0 else s2):
+            r = ctx32.plugin_bandwidth(xd)
+        assert (r.status, r.h, r.psi6, r.psi4) == (0, ref.h, ref.psi6, ref.psi4)
+
+
 def test_autotune_tables_roundtrip(kp, tmp_path):
     x = synth.bimodal(3000, 23)
     ref = oracle.plugin(x)
