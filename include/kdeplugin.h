@@ -31,8 +31,9 @@
  *    context's GPU (for example a torch tensor's data_ptr()).
  *  - A kde_stream is a hipStream_t passed as void*; NULL is the null stream.
  *  - Every call on a context is synchronous with respect to the host unless
- *    its comment says otherwise; work is enqueued on the given stream and the
- *    call waits for that stream before returning.
+ *    its comment says otherwise (kde_plugin_bandwidth_batch on device
+ *    samples and device-accessible results); work is enqueued on the given
+ *    stream and the call waits for that work before returning.
  *  - A context is not thread-safe: use one context per host thread.  The
  *    literal calls kde_psi() and kde_plugin_bandwidth() use a process-wide
  *    default context guarded by a mutex.
@@ -70,17 +71,22 @@ extern "C" {
 
 /* ------------------------------------------------------------------ enums */
 #define KDE_FP64_PLAIN 0 /* pair sums in FP64 with the printed polynomials and FP64 exp      */
-#define KDE_FP32_KAHAN 1 /* pair terms in FP32 (exp2 on the transcendental unit, Hermite
-                            factors in y^2 with exact integer coefficients), compensated
-                            per-thread sums (FP32 accumulators of at most 4 terms, added
-                            pairwise in FP32 and folded into FP64); moments, cross-block
-                            sums (exact, in fixed point) and Steps I-III, V, VII in
-                            FP64.  The one systematic error left by
-                            construction is the FP32 rounding of log2(e)/2 (relative
-                            1.3e-8) in the exponent                                       */
-#define KDE_FP32_KAHAN_EXACT 2 /* as KDE_FP32_KAHAN with log2(e)/2 carried as two FP32
-                                  terms (one more VALU op per pair)                    */
-#define KDE_FP32_POLYEXP 3 /* as KDE_FP32_KAHAN with 2^t evaluated by a degree-6 minimax
+#define KDE_FP32_COMP 1 /* the production precision: pair terms in FP32 (exp2 on the
+                           transcendental unit, Hermite factors in y^2 with exact integer
+                           coefficients) with error-compensated per-thread sums.  The
+                           compensation is blocking, not Kahan's algorithm: each FP32
+                           accumulator takes at most 4 terms, four of them are added
+                           pairwise in FP32 (16 terms) and the result is folded into an
+                           FP64 lane sum, so the FP32 rounding error of a partial stays
+                           that of 16 terms whatever n is (Kahan's update would cost 3
+                           more VALU operations per pair, the fold 0.3).  Moments,
+                           cross-block sums (exact, in fixed point) and Steps I-III, V,
+                           VII in FP64.  The one systematic error left by construction
+                           is the FP32 rounding of log2(e)/2 (relative 1.3e-8) in the
+                           exponent                                                      */
+#define KDE_FP32_COMP_EXACT 2 /* as KDE_FP32_COMP with log2(e)/2 carried as two FP32
+                                 terms (one more VALU op per pair)                       */
+#define KDE_FP32_POLYEXP 3 /* as KDE_FP32_COMP with 2^t evaluated by a degree-6 minimax
                               polynomial (Remez exchange, FP32 coefficients, relative
                               error 1.6e-8) on the FMA pipes instead of the
                               transcendental unit, after t = n + f, n = round(t)      */
@@ -102,7 +108,8 @@ typedef void* kde_stream;
 
 typedef struct {
     int32_t device;     /* HIP device ordinal (default 0)                                  */
-    int32_t precision;  /* KDE_FP64_PLAIN (default), KDE_FP32_KAHAN or KDE_FP32_KAHAN_EXACT  */
+    int32_t precision;  /* KDE_FP64_PLAIN (default), KDE_FP32_COMP, KDE_FP32_COMP_EXACT,
+                           KDE_FP32_POLYEXP or KDE_Q32_32                                 */
     int64_t mem_budget; /* bytes of device workspace this context may hold; 0 = no limit    */
     const char* tune_table; /* path of an autotune table written by kde_autotune, or NULL
                                for the built-in tile configuration                          */
@@ -168,8 +175,12 @@ KDE_API int kde_ctx_last_timeline(const kde_ctx* ctx, int64_t sample, double* ms
 /* ------------------------------------------------------- literal calls */
 
 /* Psi_r(g) of equations (6)-(7) (Steps IV/VI with a caller-chosen g) for
- * r in {4, 6}: host pointer x[0..n), n >= 1, g > 0.  Synchronous, FP64
- * plain, default context.  Returns NaN on error. */
+ * r in {4, 6}: host pointer x[0..n), n >= 1, g > 0.  Any finite sample is
+ * valid: n = 1 gives K^(r)(0) / g^(r+1), and ties are ordinary K^(r)(0) terms
+ * (Step I only centres the data here, so a sample without spread is no
+ * error).  Synchronous, FP64 plain, default context.  Returns NaN on error
+ * (null x, n < 1, r not in {4, 6}, g not finite and positive, NaN or Inf in
+ * x). */
 KDE_API double kde_psi(const double* x, int64_t n, int r, double g);
 
 /* h of Algorithm 1 (Steps I-VII) for host samples x[0..n), n >= 2.
@@ -178,10 +189,13 @@ KDE_API double kde_plugin_bandwidth(const double* x, int64_t n);
 
 /* --------------------------------------------------------- context calls */
 
-/* Psi_r(g) for samples x (mem_kind KDE_MEM_HOST/DEVICE, dtype KDE_F64/F32),
- * in the context's precision.  *out receives the value.  Synchronous. */
-KDE_API int kde_psi_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r,
-               double g, kde_stream stream, double* out);
+/* Psi_r(g) of equations (6)-(7) for samples x[0..n), n >= 1 (as kde_psi),
+ * r in {4, 6}, g > 0, with x in host or device memory (mem_kind
+ * KDE_MEM_HOST/DEVICE) as FP64 or FP32 values (dtype KDE_F64/F32), in the
+ * context's precision.  *out receives the value.  Errors as kde_psi, plus
+ * KDE_ENOMEM / KDE_EDEVICE.  Synchronous. */
+KDE_API int kde_psi_ex(kde_ctx* ctx, const void* x, int64_t n, int r, double g, int mem_kind,
+               int dtype, kde_stream stream, double* out);
 
 /* Algorithm 1 for one sample; *out receives every intermediate.  The result's
  * status field repeats the return code.  Synchronous. */
@@ -194,7 +208,17 @@ KDE_API int kde_plugin_bandwidth_ex(kde_ctx* ctx, const void* x, int64_t n, int 
  * filled for every k; the return value is KDE_OK when the launch itself
  * succeeded, and per-sample failures are reported in out[k].status.  Each
  * out[k] is bitwise identical to what kde_plugin_bandwidth_ex returns for the
- * same sample on the same context.  Synchronous. */
+ * same sample on the same context.
+ *
+ * Asynchronous when the samples are device memory (mem_kind KDE_MEM_DEVICE)
+ * and out is device-accessible (memory on the context's GPU, or pinned host
+ * memory from hipHostMalloc): the call enqueues the launch and the writing
+ * of out[0..count) on `stream` and returns; the caller synchronizes the
+ * stream before reading out, and keeps xs[k] and out alive until then.  A
+ * later call on the same context (any stream) is ordered after this one's
+ * use of the shared work list where it needs to be, so calls on several
+ * streams may be in flight at once.  Otherwise (host samples, or out in
+ * ordinary pageable host memory) the call returns when out is filled. */
 KDE_API int kde_plugin_bandwidth_batch(kde_ctx* ctx, const void* const* xs, const int64_t* ns,
                                int64_t count, int mem_kind, kde_result* out, kde_stream stream);
 
@@ -215,8 +239,8 @@ KDE_API int kde_psi_item_geometry(const kde_ctx* ctx, int64_t n, int64_t item, i
  * This is one shard of Step IV/VI: the shards of a partition of
  * [0, kde_psi_num_items) add up to the full strict-upper-triangle sum.
  * Synchronous. */
-KDE_API int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r,
-                  double g, int64_t item_begin, int64_t item_end, kde_stream stream,
+KDE_API int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int r, double g, int mem_kind,
+                  int dtype, int64_t item_begin, int64_t item_end, kde_stream stream,
                   double* partial);
 
 /* ------------------------------------------------------ density evaluation */

@@ -665,7 +665,7 @@ __device__ __forceinline__ void pair16_loop_r6_f32(uint32_t addr, int32_t cnt, f
         : "v80", "v81", "v82", "v83", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101", "v125", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "v144", "v145", "v146", "v147", "v148", "v149", "v150", "v151", "v152", "v153", "v154", "v155", "v156", "v157", "scc", "memory");
 }
 
-// The exact-k variant (KDE_FP32_KAHAN_EXACT) of the Step IV loop above:
+// The exact-k variant (KDE_FP32_COMP_EXACT) of the Step IV loop above:
 // per pair d = ui - xj, Y = d d, a = fma(Y, k_hi, Y k_lo), e = 2^(-a),
 // p = ((Y - 15) Y + 45) Y - 15, column c into accumulator c, the same fold.
 // The compiler's own code for the step, registers included, written out
@@ -1282,9 +1282,12 @@ __device__ q32 pair_item_q32(const View& d, int32_t rb, int32_t cb, double mean,
     const int64_t r0 = (int64_t)rb * TI;
     const int64_t wlo = r0 + (int64_t)wave * WAVE * R;
     const int64_t whi = wlo + WAVE * R;
-    // z-scores (the reciprocal of sigma, not a division) and the reciprocal bandwidth in z units
-    const double inv_sigma = 1.0 / sigma;
-    const q32 ginv = q_from(sigma * scale);
+    // z-scores (the reciprocal of sigma, not a division) and the reciprocal
+    // bandwidth in z units.  Psi_r(g) of a sample without spread (n = 1 or
+    // ties only) has no z-score: its values are then taken in units of g.
+    const double zs = sigma > 0.0 && isfinite(sigma) ? sigma : 1.0 / scale;
+    const double inv_sigma = 1.0 / zs;
+    const q32 ginv = q_from(zs * scale);
 
     q32 zi[R], acc[R];
 #pragma unroll
@@ -1373,7 +1376,14 @@ __device__ Published finalize_stage(const View& d, State* st, int32_t stage, dou
         const double sigma = sqrt(tot / (nd - 1.0));
         st_f64(&st->sigma, sigma);
         st_f64(&st->maxdev, aux);
-        if (status == 0 && !(sigma > 0.0 && isfinite(sigma))) { set_status(st, KDE_EDEGENERATE); status = KDE_EDEGENERATE; }
+        // sigma = 0 makes Psi8 of Step II infinite: only the full selection
+        // needs it.  For Psi_r(g) with a given g, Step I only centres the
+        // data, and n = 1 or a sample of ties is an ordinary input whose
+        // pairs are K(0) terms (equations (6)-(7)).
+        if (d.mode == MODE_PLUGIN && status == 0 && !(sigma > 0.0 && isfinite(sigma))) {
+            set_status(st, KDE_EDEGENERATE);
+            status = KDE_EDEGENERATE;
+        }
         double g;
         if (d.mode == MODE_PLUGIN) {
             st_f64(&st->psi8, 105.0 / (32.0 * sqrt(pi) * pow(sigma, 9.0)));
@@ -1831,6 +1841,42 @@ hipError_t launch_init(State* states, Pub* pubs, int32_t count, uint32_t* ticket
     const int64_t cover = (int64_t)count * kPubReplicas;
     const int blocks = cover > 0 ? (int)((cover + threads - 1) / threads) : 1;
     hipLaunchKernelGGL(k_init, dim3(blocks), dim3(threads), 0, s, states, pubs, count, ticket);
+    return hipGetLastError();
+}
+
+// Results of an asynchronous batch call, written where the caller asked
+// (device memory or pinned host memory): out[k] from state outmap[2k], or a
+// sample the host rejected with status outmap[2k + 1].  The same fields as the
+// host read-back fills, so both routes give the same bits.
+__global__ void k_results(const State* states, const int32_t* outmap, int64_t n_out, kde_result* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_out) return;
+    const int32_t q = outmap[2 * k];
+    kde_result r = {};
+    if (q < 0) {
+        r.h = __longlong_as_double(0x7ff8000000000000ll);
+        r.status = outmap[2 * k + 1];
+    } else {
+        const State& s = states[q];
+        r.h = s.status ? __longlong_as_double(0x7ff8000000000000ll) : s.h;
+        r.mean = s.mean;
+        r.sigma = s.sigma;
+        r.psi8 = s.psi8;
+        r.g1 = s.g1;
+        r.psi6 = s.psi6;
+        r.g2 = s.g2;
+        r.psi4 = s.psi4;
+        r.status = s.status;
+    }
+    out[k] = r;
+}
+
+hipError_t launch_results(const State* states, const int32_t* outmap, int64_t n_out, kde_result* out,
+                          hipStream_t s) {
+    if (n_out <= 0) return hipSuccess;
+    const int threads = 64;
+    hipLaunchKernelGGL(k_results, dim3((unsigned)((n_out + threads - 1) / threads)), dim3(threads), 0, s, states,
+                       outmap, n_out, out);
     return hipGetLastError();
 }
 

@@ -353,8 +353,14 @@ int upload_plan(kde_ctx* c, Plan& p) {
     if ((st = p.d_slots.ensure(sizeof(Slot) * (size_t)std::max<int64_t>(1, p.n_slots), "slots"))) return st;
     if ((st = p.d_ticket.ensure(256, "ticket"))) return st;
     HIPCHK(hipHostMalloc((void**)&p.h_states, sizeof(State) * std::max(1, p.count), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&p.h_descs, sizeof(Desc) * std::max(1, p.count), hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&p.ev_upload, hipEventDisableTiming));
     if (!p.items.empty())
         HIPCHK(hipMemcpy(p.d_items.p, p.items.data(), sizeof(Item) * p.items.size(), hipMemcpyHostToDevice));
+    if (!p.outmap.empty()) {
+        if ((st = p.d_outmap.ensure(sizeof(int32_t) * p.outmap.size(), "batch output map"))) return st;
+        HIPCHK(hipMemcpy(p.d_outmap.p, p.outmap.data(), sizeof(int32_t) * p.outmap.size(), hipMemcpyHostToDevice));
+    }
     int64_t per_stage[NUM_STAGES] = {0};
     for (const Item& it : p.items) ++per_stage[it.stage];
     p.grid = grid_for(c, *std::max_element(per_stage, per_stage + NUM_STAGES));
@@ -383,7 +389,15 @@ LaunchArgs args_for(const kde_ctx* c, Plan& p) {
 // (once before the first): the caller waits for the event recorded between
 // the two only, and the next call's kernel starts without a kernel boundary
 // in front of it.
-int run_plan(kde_ctx* c, Plan& p, hipStream_t s) {
+//
+// Everything a call changes on the device is ordered on the caller's stream
+// after the previous replay of the plan (and the reset behind it): the
+// descriptors go up from pinned staging by a stream-ordered copy, so a call
+// may return before its launch has run (asynchronous batch calls) and the
+// next call still cannot overwrite what a replay in flight reads.  out, when
+// given, is device-accessible memory that receives the batch results on the
+// stream (k_results) before the reset.
+int run_plan(kde_ctx* c, Plan& p, hipStream_t s, kde_result* out = nullptr, bool timed = true) {
     if (!p.exec) {
         hipStream_t cap;
         HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -413,9 +427,21 @@ int run_plan(kde_ctx* c, Plan& p, hipStream_t s) {
         // the reset after the previous replay ran on another stream
         HIPCHK(hipStreamWaitEvent(s, p.ev_reset, 0));
     }
-    HIPCHK(hipEventRecord(c->ev0, s));
+    if (p.descs_dirty) {
+        // the staging buffer is rewritten only once its previous upload has
+        // been done (long ago, as a rule)
+        HIPCHK(hipEventSynchronize(p.ev_upload));
+        std::memcpy(p.h_descs, p.descs.data(), sizeof(Desc) * p.count);
+        HIPCHK(hipMemcpyAsync(p.d_descs.p, p.h_descs, sizeof(Desc) * p.count, hipMemcpyHostToDevice, s));
+        HIPCHK(hipEventRecord(p.ev_upload, s));
+        p.descs_dirty = false;
+    }
+    if (timed) HIPCHK(hipEventRecord(c->ev0, s));
     HIPCHK(hipGraphLaunch(p.exec, s));
-    HIPCHK(hipEventRecord(c->ev1, s));
+    if (timed) HIPCHK(hipEventRecord(c->ev1, s));
+    if (out)
+        HIPCHK(launch_results((const State*)p.d_states.p, (const int32_t*)p.d_outmap.p,
+                              (int64_t)p.outmap.size() / 2, out, s));
     HIPCHK(launch_init((State*)p.d_states.p, (Pub*)p.d_pubs.p, p.count, (uint32_t*)p.d_ticket.p, s));
     HIPCHK(hipEventRecord(p.ev_reset, s));
     p.reset_stream = s;
@@ -432,29 +458,28 @@ Plan* find_plan(kde_ctx* c, const std::string& key) {
     return nullptr;
 }
 
-int get_plan(kde_ctx* c, const std::string& key, const std::vector<SampleSpec>& ss, Plan** out) {
+int get_plan(kde_ctx* c, const std::string& key, const std::vector<SampleSpec>& ss, Plan** out,
+             const std::vector<int32_t>* outmap = nullptr) {
     Plan* p = find_plan(c, key);
     if (!p) {
         auto np = std::make_unique<Plan>();
         np->key = key;
         build_items(c, *np, ss);
+        if (outmap) np->outmap = *outmap;
         int st = upload_plan(c, *np);
         if (st) return st;
         c->plans.push_front(std::move(np));
         while (c->plans.size() > c->max_plans) c->plans.pop_back();
         p = c->plans.front().get();
     }
-    // refresh descriptors if the sample pointers (or psi parameters) changed
-    bool same = p->descs_valid && (int32_t)ss.size() == p->count;
-    for (size_t k = 0; same && k < ss.size(); ++k)
-        same = p->descs[k].x == ss[k].x && p->descs[k].psi_g == ss[k].psi_g;
-    if (!same) {
-        for (size_t k = 0; k < ss.size(); ++k) {
+    // descriptors are uploaded again (in run_plan, ordered on the call's
+    // stream) if the sample pointers (or psi parameters) changed
+    for (size_t k = 0; k < ss.size(); ++k) {
+        if (p->descs[k].x != ss[k].x || p->descs[k].psi_g != ss[k].psi_g) {
             p->descs[k].x = ss[k].x;
             p->descs[k].psi_g = ss[k].psi_g;
+            p->descs_dirty = true;
         }
-        HIPCHK(hipMemcpy(p->d_descs.p, p->descs.data(), sizeof(Desc) * p->count, hipMemcpyHostToDevice));
-        p->descs_valid = true;
     }
     *out = p;
     return KDE_OK;
@@ -586,8 +611,8 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     kde_options o;
     kde_options_init(&o);
     if (opt) o = *opt;
-    if (o.precision != KDE_FP64_PLAIN && o.precision != KDE_FP32_KAHAN &&
-        o.precision != KDE_FP32_KAHAN_EXACT && o.precision != KDE_FP32_POLYEXP && o.precision != KDE_Q32_32)
+    if (o.precision != KDE_FP64_PLAIN && o.precision != KDE_FP32_COMP &&
+        o.precision != KDE_FP32_COMP_EXACT && o.precision != KDE_FP32_POLYEXP && o.precision != KDE_Q32_32)
         return set_err(KDE_EINVAL, "bad precision");
     if (o.rows_per_lane != 0 && o.rows_per_lane != 1 && o.rows_per_lane != 2 && o.rows_per_lane != 4)
         return set_err(KDE_EINVAL, "rows_per_lane must be 0, 1, 2 or 4");
@@ -670,7 +695,7 @@ int kde_psi_item_geometry(const kde_ctx* c, int64_t n, int64_t item, int64_t* r0
     return ok();
 }
 
-int kde_psi_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r, double g,
+int kde_psi_ex(kde_ctx* ctx, const void* x, int64_t n, int r, double g, int mem_kind, int dtype,
                kde_stream stream, double* out) {
     if (!ctx || !out) return set_err(KDE_EINVAL, "null context or output");
     State s{};
@@ -681,7 +706,7 @@ int kde_psi_ex(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, 
     return ok();
 }
 
-int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int mem_kind, int dtype, int r, double g,
+int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int r, double g, int mem_kind, int dtype,
                   int64_t item_begin, int64_t item_end, kde_stream stream, double* partial) {
     if (!ctx || !partial) return set_err(KDE_EINVAL, "null context or output");
     const int64_t np = n >= 1 ? pair_item_count(pair_geom(ctx, n)) : 0;
@@ -726,6 +751,20 @@ int kde_plugin_bandwidth_ex(kde_ctx* c, const void* x, int64_t n, int mem_kind, 
     return ok();
 }
 
+// Device-accessible address of out for the results kernel, or nullptr when out
+// is ordinary (pageable) host memory, which only the host can fill.
+static kde_result* device_view(const kde_ctx* c, kde_result* out) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, out) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged)
+        return a.device == c->device ? out : nullptr;
+    if (a.type == hipMemoryTypeHost) return (kde_result*)(a.devicePointer ? a.devicePointer : (void*)out);
+    return nullptr;
+}
+
 int kde_plugin_bandwidth_batch(kde_ctx* c, const void* const* xs, const int64_t* ns, int64_t count,
                                int mem_kind, kde_result* out, kde_stream stream) {
     if (!c || !xs || !ns || !out || count < 1) return set_err(KDE_EINVAL, "bad batch arguments");
@@ -733,19 +772,25 @@ int kde_plugin_bandwidth_batch(kde_ctx* c, const void* const* xs, const int64_t*
     if (mem_kind != KDE_MEM_HOST && mem_kind != KDE_MEM_DEVICE) return set_err(KDE_EINVAL, "bad mem_kind");
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard dg(c->device);
-    std::vector<SampleSpec> ss((size_t)count);
+    // asynchronous when the samples are on the device and out is
+    // device-accessible: the results are then written by the device, on s
+    kde_result* dout = mem_kind == KDE_MEM_DEVICE ? device_view(c, out) : nullptr;
+    std::vector<int32_t> status((size_t)count, KDE_OK);
     std::vector<int64_t> valid;
-    std::string key = "batch";
+    std::string key = dout ? "batch-async" : "batch";
     key.reserve(16 * (size_t)count);
     size_t host_bytes = 0;
     for (int64_t k = 0; k < count; ++k) {
-        std::memset(&out[k], 0, sizeof(kde_result));
-        out[k].h = NAN;
         const int st = check_x(xs[k], ns[k], 2, mem_kind, KDE_F64);
-        out[k].status = st;
+        status[(size_t)k] = st;
         if (st == KDE_OK) {
             valid.push_back(k);
             host_bytes += (size_t)ns[k] * 8;
+        }
+        if (!dout) {
+            std::memset(&out[k], 0, sizeof(kde_result));
+            out[k].h = NAN;
+            out[k].status = st;
         }
     }
     if (valid.empty()) return set_err(KDE_EINVAL, "no valid sample in the batch");
@@ -767,9 +812,29 @@ int kde_plugin_bandwidth_batch(kde_ctx* c, const void* const* xs, const int64_t*
         vs.push_back(SampleSpec{dx, ns[k], KDE_F64, MODE_PLUGIN, 0, 0.0, 0, -1});
         key += ":" + std::to_string(ns[k]);
     }
+    std::vector<int32_t> outmap;
+    if (dout) {
+        // the output map is part of the plan: the positions and statuses of
+        // rejected samples go into the key
+        outmap.assign(2 * (size_t)count, 0);
+        int32_t q = 0;
+        for (int64_t k = 0; k < count; ++k) {
+            if (status[(size_t)k] == KDE_OK) {
+                outmap[2 * k] = q++;
+            } else {
+                outmap[2 * k] = -1;
+                outmap[2 * k + 1] = status[(size_t)k];
+                key += "|x" + std::to_string(k) + "=" + std::to_string(status[(size_t)k]);
+            }
+        }
+    }
     Plan* p = nullptr;
     int st;
-    if ((st = get_plan(c, key, vs, &p))) return st;
+    if ((st = get_plan(c, key, vs, &p, dout ? &outmap : nullptr))) return st;
+    if (dout) {
+        if ((st = run_plan(c, *p, s, dout, false))) return st;
+        return ok();
+    }
     if ((st = run_plan(c, *p, s))) return st;
     if ((st = finish(c, *p, s))) return st;
     for (size_t q = 0; q < valid.size(); ++q) {
@@ -804,7 +869,7 @@ double kde_psi(const double* x, int64_t n, int r, double g) {
     kde_ctx* c = default_ctx();
     if (!c) return NAN;
     double v = NAN;
-    if (kde_psi_ex(c, x, n, KDE_MEM_HOST, KDE_F64, r, g, nullptr, &v) != KDE_OK) return NAN;
+    if (kde_psi_ex(c, x, n, r, g, KDE_MEM_HOST, KDE_F64, nullptr, &v) != KDE_OK) return NAN;
     return v;
 }
 

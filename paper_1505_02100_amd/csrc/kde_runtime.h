@@ -15,6 +15,8 @@
 
 namespace kde {
 hipError_t launch_init(State* states, Pub* pubs, int32_t count, uint32_t* ticket, hipStream_t s);
+hipError_t launch_results(const State* states, const int32_t* outmap, int64_t n_out, kde_result* out,
+                          hipStream_t s);
 hipError_t launch_persistent(int prec, int R, int grid, hipStream_t s, const LaunchArgs& a);
 hipError_t persistent_occupancy(int prec, int R, int* blocks_per_cu);
 }  // namespace kde
@@ -56,9 +58,16 @@ struct Plan {
     int32_t count = 0;                // samples
     std::vector<Item> items;
     std::vector<Desc> descs;          // host copy of what is on the device
-    bool descs_valid = false;
     DevBuf d_items, d_descs, d_states, d_pubs, d_slots, d_ticket;
     State* h_states = nullptr;        // pinned
+    Desc* h_descs = nullptr;          // pinned staging of descriptor uploads
+    bool descs_dirty = true;          // descs differ from what the device holds
+    hipEvent_t ev_upload = nullptr;   // recorded after the last upload from h_descs
+    // Batch results written on the device (asynchronous batch calls): out[k]
+    // takes the state of sample outmap[2k] >= 0, or the status outmap[2k + 1]
+    // of a sample the host already rejected.
+    std::vector<int32_t> outmap;
+    DevBuf d_outmap;
     int64_t n_slots = 0;
     hipGraphExec_t exec = nullptr;
     bool primed = false;              // states reset once before the first replay
@@ -66,12 +75,17 @@ struct Plan {
     hipStream_t reset_stream = nullptr;  // the stream that reset was issued on
     int grid = 0;
     ~Plan() {
+        // a replay may still be in flight (asynchronous calls): let it finish
+        if (ev_reset) (void)hipEventSynchronize(ev_reset);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (ev_reset) (void)hipEventDestroy(ev_reset);
+        if (ev_upload) (void)hipEventDestroy(ev_upload);
         if (h_states) (void)hipHostFree(h_states);
+        if (h_descs) (void)hipHostFree(h_descs);
     }
     size_t device_bytes() const {
-        return d_items.bytes + d_descs.bytes + d_states.bytes + d_pubs.bytes + d_slots.bytes + d_ticket.bytes;
+        return d_items.bytes + d_descs.bytes + d_states.bytes + d_pubs.bytes + d_slots.bytes + d_ticket.bytes +
+               d_outmap.bytes;
     }
 };
 

@@ -53,8 +53,8 @@ KDE_ETIMEOUT = -6
 KDE_EBUSY = -7
 
 KDE_FP64_PLAIN = 0
-KDE_FP32_KAHAN = 1
-KDE_FP32_KAHAN_EXACT = 2
+KDE_FP32_COMP = 1
+KDE_FP32_COMP_EXACT = 2
 KDE_FP32_POLYEXP = 3
 KDE_Q32_32 = 4
 KDE_MEM_HOST = 0
@@ -140,7 +140,7 @@ _sig("kde_ctx_destroy", None, _P)
 _sig("kde_ctx_config", ctypes.c_int, _P, _PI32, _PI32, _PI32, _PI32)
 _sig("kde_psi", _D, ctypes.POINTER(_D), _I64, ctypes.c_int, _D)
 _sig("kde_plugin_bandwidth", _D, ctypes.POINTER(_D), _I64)
-_sig("kde_psi_ex", ctypes.c_int, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _P,
+_sig("kde_psi_ex", ctypes.c_int, _P, _P, _I64, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, _P,
      ctypes.POINTER(_D))
 _sig("kde_plugin_bandwidth_ex", ctypes.c_int, _P, _P, _I64, ctypes.c_int, ctypes.c_int, _P,
      ctypes.POINTER(kde_result))
@@ -160,7 +160,7 @@ _sig("kde_server_drain", ctypes.c_int, _P)
 _sig("kde_autotune", ctypes.c_int, ctypes.POINTER(kde_options), _PI64, _I32, _I32, _I32, ctypes.c_char_p,
      _I32)
 _sig("kde_psi_item_geometry", ctypes.c_int, _P, _I64, _I64, _PI64, _PI64, _PI64, _PI64)
-_sig("kde_psi_range", ctypes.c_int, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D,
+_sig("kde_psi_range", ctypes.c_int, _P, _P, _I64, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int,
      _I64, _I64, _P, ctypes.POINTER(_D))
 _sig("kde_eval_ex", ctypes.c_int, _P, _P, _I64, ctypes.c_int, ctypes.c_int, _P, _I64, ctypes.c_int, _D, _P,
      _P)
@@ -311,7 +311,7 @@ def kde_ctx_last_device_ms(ctx: int) -> float:
 def kde_psi_ex(ctx: int, x, r: int, g: float) -> float:
     s = _Samples(x)
     out = _D()
-    _check(_lib.kde_psi_ex(ctx, s.ptr, s.n, s.mem, s.dtype, int(r), float(g), s.stream,
+    _check(_lib.kde_psi_ex(ctx, s.ptr, s.n, int(r), float(g), s.mem, s.dtype, s.stream,
                            ctypes.byref(out)), "kde_psi_ex")
     return out.value
 
@@ -343,6 +343,34 @@ def kde_plugin_bandwidth_batch(ctx: int, xs: Sequence) -> List[kde_result]:
     return list(out)
 
 
+def kde_plugin_bandwidth_batch_async(ctx: int, xs: Sequence, out) -> None:
+    """Enqueue a batch of device samples (torch CUDA float64 tensors) on torch's
+    current stream; the results land in ``out`` (a torch tensor in device
+    memory or pinned host memory of at least len(xs) * sizeof(kde_result)
+    bytes) when the stream gets there.  The caller synchronizes the stream
+    and reads them with ``batch_results(out, len(xs))``."""
+    ss = [_Samples(x) for x in xs]
+    if any(s.mem != KDE_MEM_DEVICE or s.dtype != KDE_F64 for s in ss):
+        raise TypeError("asynchronous batches take torch CUDA float64 tensors")
+    m = len(ss)
+    if out.numel() * out.element_size() < m * ctypes.sizeof(kde_result):
+        raise ValueError("output buffer too small")
+    ptrs = (_P * m)(*[s.ptr for s in ss])
+    ns = (_I64 * m)(*[s.n for s in ss])
+    _check(_lib.kde_plugin_bandwidth_batch(ctx, ptrs, ns, m, KDE_MEM_DEVICE,
+                                           ctypes.cast(out.data_ptr(), ctypes.POINTER(kde_result)),
+                                           ss[0].stream), "kde_plugin_bandwidth_batch")
+
+
+def batch_results(out, count: int) -> List[kde_result]:
+    """kde_result records from a buffer written by an asynchronous batch (after
+    the caller has synchronized its stream)."""
+    host = out.cpu() if out.device.type == "cuda" else out
+    raw = bytes(host.contiguous().view(-1).numpy().view(np.uint8)[: count * ctypes.sizeof(kde_result)])
+    arr = (kde_result * count).from_buffer_copy(raw)
+    return list(arr)
+
+
 def kde_psi_num_items(ctx: int, n: int) -> int:
     v = _lib.kde_psi_num_items(ctx, int(n))
     if v < 0:
@@ -360,7 +388,7 @@ def kde_psi_item_geometry(ctx: int, n: int, item: int):
 def kde_psi_range(ctx: int, x, r: int, g: float, item_begin: int, item_end: int) -> float:
     s = _Samples(x)
     out = _D()
-    _check(_lib.kde_psi_range(ctx, s.ptr, s.n, s.mem, s.dtype, int(r), float(g), int(item_begin),
+    _check(_lib.kde_psi_range(ctx, s.ptr, s.n, int(r), float(g), s.mem, s.dtype, int(item_begin),
                               int(item_end), s.stream, ctypes.byref(out)), "kde_psi_range")
     return out.value
 
@@ -500,6 +528,9 @@ class Context:
 
     def plugin_bandwidth_batch(self, xs: Iterable):
         return kde_plugin_bandwidth_batch(self.handle, list(xs))
+
+    def plugin_bandwidth_batch_async(self, xs: Iterable, out):
+        return kde_plugin_bandwidth_batch_async(self.handle, list(xs), out)
 
     def psi_num_items(self, n):
         return kde_psi_num_items(self.handle, n)

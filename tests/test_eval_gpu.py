@@ -32,7 +32,7 @@ def kp():
 
 @pytest.fixture(scope="module")
 def ctxs(kp):
-    c = {p: kp.Context(p) for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_KAHAN)}
+    c = {p: kp.Context(p) for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_COMP)}
     yield c
     for v in c.values():
         v.close()
@@ -52,7 +52,7 @@ def test_grid_against_oracle(kp, ctxs, n, m):
     y = np.linspace(x.min() - 3 * h, x.max() + 3 * h, m)
     ref = oracle.kde_eval(x, h, y)
     _compare(ctxs[kp.KDE_FP64_PLAIN].eval(x, y, h), ref, 2 * n * U + 4 * U)
-    _compare(ctxs[kp.KDE_FP32_KAHAN].eval(x, y, h), ref, FP32_TOL)
+    _compare(ctxs[kp.KDE_FP32_COMP].eval(x, y, h), ref, FP32_TOL)
 
 
 def test_at_the_samples_unsorted_and_sorted(kp, ctxs):
@@ -63,14 +63,14 @@ def test_at_the_samples_unsorted_and_sorted(kp, ctxs):
     for y in (x[:3000].copy(), np.sort(x[:3000])):
         ref = oracle.kde_eval(x, h, y)
         _compare(ctxs[kp.KDE_FP64_PLAIN].eval(x, y, h), ref, 2 * x.size * U + 4 * U)
-        _compare(ctxs[kp.KDE_FP32_KAHAN].eval(x, y, h), ref, FP32_TOL)
+        _compare(ctxs[kp.KDE_FP32_COMP].eval(x, y, h), ref, FP32_TOL)
 
 
 def test_device_path_equals_host_path_and_is_deterministic(kp, ctxs):
     import torch
     x = synth.normal(50000, 3)
     y = np.linspace(-5, 5, 3000)
-    for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_KAHAN):
+    for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_COMP):
         host = ctxs[p].eval(x, y, 0.12)
         dev = ctxs[p].eval(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), 0.12)
         assert isinstance(dev, torch.Tensor) and dev.is_cuda
@@ -79,14 +79,14 @@ def test_device_path_equals_host_path_and_is_deterministic(kp, ctxs):
     # float32 samples: same definition on the widened values
     x32 = x.astype(np.float32)
     ref = oracle.kde_eval(x32.astype(np.float64), 0.12, y)
-    _compare(ctxs[kp.KDE_FP32_KAHAN].eval(x32, y, 0.12), ref, FP32_TOL)
+    _compare(ctxs[kp.KDE_FP32_COMP].eval(x32, y, 0.12), ref, FP32_TOL)
 
 
 def test_integrates_to_one(kp, ctxs):
     x = synth.draw("bimodal", 20000, 4)
-    h = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth(x).h
+    h = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth(x).h
     y = np.linspace(x.min() - 10 * h, x.max() + 10 * h, 20001)
-    f = ctxs[kp.KDE_FP32_KAHAN].eval(x, y, h)
+    f = ctxs[kp.KDE_FP32_COMP].eval(x, y, h)
     assert abs(np.trapezoid(f, y) - 1.0) < 1e-6
 
 
@@ -96,10 +96,10 @@ def test_full_size_lognormal_grid_sampled(kp, ctxs):
     import torch
     x = synth.workload_single_lognormal(1 << 20, 2)
     xd = torch.from_numpy(x).cuda()
-    h = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth(xd).h
+    h = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth(xd).h
     y = np.linspace(np.quantile(x, 0.001), np.quantile(x, 0.999), 4096)
     yd = torch.from_numpy(y).cuda()
-    got32 = ctxs[kp.KDE_FP32_KAHAN].eval(xd, yd, h).cpu().numpy()
+    got32 = ctxs[kp.KDE_FP32_COMP].eval(xd, yd, h).cpu().numpy()
     got64 = ctxs[kp.KDE_FP64_PLAIN].eval(xd, yd, h).cpu().numpy()
     idx = np.unique(np.concatenate([[0, 1, 255, 256, 4095], np.random.default_rng(5).integers(0, 4096, 11)]))
     ref = oracle.kde_eval(x, h, y[idx])
@@ -108,7 +108,7 @@ def test_full_size_lognormal_grid_sampled(kp, ctxs):
 
 
 def test_errors_and_empty(kp, ctxs):
-    c = ctxs[kp.KDE_FP32_KAHAN]
+    c = ctxs[kp.KDE_FP32_COMP]
     x = synth.normal(100, 1)
     assert c.eval(x, np.zeros(0), 0.5).size == 0
     with pytest.raises(kp.KdeError) as e:

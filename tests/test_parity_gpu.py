@@ -6,7 +6,7 @@ Tolerances (relative):
     implementations and a reciprocal instead of a division for 1/g; the
     rounding error of a sum of n^2 terms with cancellation factor
     k = sum|terms| / |sum| stays below ~1e-14 k for the sizes tested.
-  * FP32 Kahan: h within 1e-6 (the bound the FP32 path is built to);
+  * FP32 (compensated sums): h within 1e-6 (the bound the FP32 path is built to);
     Psi6 and Psi4 within 2e-5 (their FP32 rounding is amplified by the
     cancellation inside the Hermite factor and the sum).
 """
@@ -40,14 +40,14 @@ def ctx64(kp):
 
 @pytest.fixture(scope="module")
 def ctx32(kp):
-    c = kp.Context(kp.KDE_FP32_KAHAN)
+    c = kp.Context(kp.KDE_FP32_COMP)
     yield c
     c.close()
 
 
 @pytest.fixture(scope="module")
 def ctx32x(kp):
-    c = kp.Context(kp.KDE_FP32_KAHAN_EXACT)
+    c = kp.Context(kp.KDE_FP32_COMP_EXACT)
     yield c
     c.close()
 
@@ -73,6 +73,9 @@ def _rel(a, b):
 def _check(res, ref, tol_h, tol_psi):
     assert res.status == 0
     assert _rel(res.sigma, ref.sigma) < 1e-13
+    # Step II in FP64 on both sides from the same sigma (sigma^9 amplifies
+    # sigma's rounding ninefold)
+    assert _rel(res.psi8, ref.psi8) < 1e-11, (res.psi8, ref.psi8)
     assert _rel(res.g1, ref.g1) < 1e-13
     assert _rel(res.psi6, ref.psi6) < tol_psi, (res.psi6, ref.psi6)
     assert _rel(res.g2, ref.g2) < tol_psi
@@ -364,16 +367,16 @@ def test_autotune_tables_roundtrip(kp, tmp_path):
     x = synth.bimodal(3000, 23)
     ref = oracle.plugin(x)
     p1 = str(tmp_path / "single.json")
-    t1 = kp.kde_autotune(kp.KDE_FP32_KAHAN, [1024, 4096], p1, mode=kp.KDE_TUNE_SINGLE, reps=2)
+    t1 = kp.kde_autotune(kp.KDE_FP32_COMP, [1024, 4096], p1, mode=kp.KDE_TUNE_SINGLE, reps=2)
     assert t1["rows_per_lane"] in (1, 2, 4) and len(t1["targets"]) == 2
-    with kp.Context(kp.KDE_FP32_KAHAN, tune_table=p1) as c:
+    with kp.Context(kp.KDE_FP32_COMP, tune_table=p1) as c:
         cfg = c.config()
         assert cfg["rows_per_lane"] == t1["rows_per_lane"] and cfg["blocks_per_cu"] == t1["blocks_per_cu"]
         _check(c.plugin_bandwidth(x), ref, TOL32_H, TOL32_PSI)
     p2 = str(tmp_path / "batch.json")
-    t2 = kp.kde_autotune(kp.KDE_FP32_KAHAN, [300, 1000, 2500], p2, mode=kp.KDE_TUNE_BATCH, reps=2)
+    t2 = kp.kde_autotune(kp.KDE_FP32_COMP, [300, 1000, 2500], p2, mode=kp.KDE_TUNE_BATCH, reps=2)
     assert t2["pair_budget"] > 0
-    with kp.Context(kp.KDE_FP32_KAHAN, tune_table=p2) as c:
+    with kp.Context(kp.KDE_FP32_COMP, tune_table=p2) as c:
         res = c.plugin_bandwidth_batch([x, x[:500]])
         _check(res[0], ref, TOL32_H, TOL32_PSI)
     with pytest.raises(kp.KdeError):

@@ -19,7 +19,7 @@ def kp():
 
 @pytest.fixture(scope="module")
 def ctx(kp):
-    c = kp.Context(kp.KDE_FP32_KAHAN)
+    c = kp.Context(kp.KDE_FP32_COMP)
     yield c
     c.close()
 
