@@ -103,7 +103,7 @@ def bench_batch(args):
     import torch
     from paper_1505_02100_amd import kdeplugin as kp
     from paper_1505_02100_amd import synth
-    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
+    prec = {"fp32": kp.KDE_FP32_COMP, "fp32x": kp.KDE_FP32_COMP_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
             "q32": kp.KDE_Q32_32, "fp64": kp.KDE_FP64_PLAIN}
     xs, names = synth.workload_batch(512, 3)
     xds = [torch.from_numpy(x).cuda() for x in xs]
@@ -183,7 +183,7 @@ def bench_eval(args):
     import torch
     from paper_1505_02100_amd import kdeplugin as kp
     from paper_1505_02100_amd import synth
-    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
+    prec = {"fp32": kp.KDE_FP32_COMP, "fp32x": kp.KDE_FP32_COMP_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
             "q32": kp.KDE_Q32_32, "fp64": kp.KDE_FP64_PLAIN}
     x = synth.workload_single_lognormal(1 << 20, 2)
     n, m = x.size, 4096
@@ -246,7 +246,7 @@ def bench_serve(args):
     from paper_1505_02100_amd import kdeplugin as kp
     from paper_1505_02100_amd import synth
     from paper_1505_02100_amd.server import serve_trace
-    prec = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
+    prec = {"fp32": kp.KDE_FP32_COMP, "fp32x": kp.KDE_FP32_COMP_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
             "q32": kp.KDE_Q32_32, "fp64": kp.KDE_FP64_PLAIN}
     trace = synth.serving_trace(rate=args.rate, duration=args.duration, master=4)
     # items of about 2^24 pairs for every request size: a step of 2^36 pairs then
@@ -338,7 +338,7 @@ def main():
 
     from paper_1505_02100_amd import kdeplugin as kp
 
-    prec_code = {"fp32": kp.KDE_FP32_KAHAN, "fp32x": kp.KDE_FP32_KAHAN_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
+    prec_code = {"fp32": kp.KDE_FP32_COMP, "fp32x": kp.KDE_FP32_COMP_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
                  "q32": kp.KDE_Q32_32, "fp64": kp.KDE_FP64_PLAIN}[args.precision]
     w = WORKLOADS[args.workload]
     x = make_sample(w)

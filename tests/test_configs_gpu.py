@@ -35,7 +35,7 @@ def kp():
 
 @pytest.fixture(scope="module")
 def ctxs(kp):
-    c = {p: kp.Context(p) for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT,
+    c = {p: kp.Context(p) for p in (kp.KDE_FP64_PLAIN, kp.KDE_FP32_COMP, kp.KDE_FP32_COMP_EXACT,
                                     kp.KDE_FP32_POLYEXP)}
     yield c
     for v in c.values():
@@ -53,7 +53,7 @@ def test_bimodal_65536_full_oracle(kp, ctxs):
     xd = torch.from_numpy(x).cuda()
     r64 = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth(xd)
     assert _rel(r64.h, ref.h) < 1e-12 and _rel(r64.psi6, ref.psi6) < 1e-12 and _rel(r64.psi4, ref.psi4) < 1e-12
-    for p in (kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT, kp.KDE_FP32_POLYEXP):
+    for p in (kp.KDE_FP32_COMP, kp.KDE_FP32_COMP_EXACT, kp.KDE_FP32_POLYEXP):
         r = ctxs[p].plugin_bandwidth(xd)
         assert _rel(r.h, ref.h) < 1e-6, (p, r.h, ref.h)
         assert _rel(r.psi6, ref.psi6) < 1e-5 and _rel(r.psi4, ref.psi4) < 5e-6
@@ -91,7 +91,7 @@ def test_lognormal_1m_sampled_items_and_properties(kp, ctxs):
     r64 = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth(xd)
     assert r64.status == 0 and r64.psi6 < 0 < r64.psi4
     # sampled items of the Step IV stage at the FP64 path's g1, each against the oracle
-    for p, eps in ((kp.KDE_FP64_PLAIN, 1e-13), (kp.KDE_FP32_KAHAN, 2e-6)):
+    for p, eps in ((kp.KDE_FP64_PLAIN, 1e-13), (kp.KDE_FP32_COMP, 2e-6)):
         ctx = ctxs[p]
         m = ctx.psi_num_items(n)
         rng = np.random.default_rng(11)
@@ -104,7 +104,7 @@ def test_lognormal_1m_sampled_items_and_properties(kp, ctxs):
     # scale and shift equivariance h(aX + b) = |a| h(X), and FP32 against FP64
     hb = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth(torch.from_numpy(base).cuda()).h
     assert _rel(r64.h, 1e3 * hb) < 1e-10
-    for p in (kp.KDE_FP32_KAHAN, kp.KDE_FP32_KAHAN_EXACT, kp.KDE_FP32_POLYEXP):
+    for p in (kp.KDE_FP32_COMP, kp.KDE_FP32_COMP_EXACT, kp.KDE_FP32_POLYEXP):
         r = ctxs[p].plugin_bandwidth(xd)
         assert _rel(r.h, r64.h) < 1e-6, (p, r.h, r64.h)
 
@@ -114,11 +114,11 @@ def test_serving_largest_request_4m(kp, ctxs):
     n = 4_000_000
     x = synth.draw("t3", n, 41)
     xd = torch.from_numpy(x).cuda()
-    r32 = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth(xd)
+    r32 = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth(xd)
     assert r32.status == 0 and r32.psi6 < 0 < r32.psi4
     # sampled items of both pair stages at the selection's own g1 and g2 (items
     # from the narrow end of the list: the oracle's block sums stay quick)
-    ctx = ctxs[kp.KDE_FP32_KAHAN]
+    ctx = ctxs[kp.KDE_FP32_COMP]
     m = ctx.psi_num_items(n)
     for r, g in ((6, r32.g1), (4, r32.g2)):
         for k in (m - 400, m - 50, m - 1):
@@ -127,9 +127,9 @@ def test_serving_largest_request_4m(kp, ctxs):
             ref = oracle.block_sum(x, r, g, r0, r1, c0, c1)
             bound = 2e-6 * _abs_block_sum(x, r, g, r0, r1, c0, c1) + 1e-300
             assert abs(got - ref) <= bound, (r, k, got, ref, bound)
-    rx = ctxs[kp.KDE_FP32_KAHAN_EXACT].plugin_bandwidth(xd)
+    rx = ctxs[kp.KDE_FP32_COMP_EXACT].plugin_bandwidth(xd)
     assert _rel(r32.h, rx.h) < 1e-6
-    r2 = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth(torch.from_numpy(2.0 * x).cuda())
+    r2 = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth(torch.from_numpy(2.0 * x).cuda())
     assert _rel(r2.h, 2.0 * r32.h) < 1e-6
 
 
@@ -144,7 +144,7 @@ def test_batch_512(kp, ctxs, batch512):
     xs, _ = batch512
     xds = [torch.from_numpy(x).cuda() for x in xs]
     b64 = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth_batch(xds)
-    b32 = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth_batch(xds)
+    b32 = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth_batch(xds)
     assert all(r.status == 0 for r in b64) and all(r.status == 0 for r in b32)
     worst = max(_rel(a.h, b.h) for a, b in zip(b32, b64))
     assert worst < 1e-6, worst
@@ -157,5 +157,5 @@ def test_batch_512(kp, ctxs, batch512):
         assert _rel(b32[k].h, ref.h) < 1e-6, (k, xs[k].size)
     # a batch result is bitwise the single-call result (decomposition depends on n only)
     for k in (0, 1, 77, 311, 511):
-        s = ctxs[kp.KDE_FP32_KAHAN].plugin_bandwidth(xds[k])
+        s = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth(xds[k])
         assert (s.h, s.psi6, s.psi4) == (b32[k].h, b32[k].psi6, b32[k].psi4)
