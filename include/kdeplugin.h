@@ -222,6 +222,43 @@ KDE_API int kde_plugin_bandwidth_ex(kde_ctx* ctx, const void* x, int64_t n, int 
 KDE_API int kde_plugin_bandwidth_batch(kde_ctx* ctx, const void* const* xs, const int64_t* ns,
                                int64_t count, int mem_kind, kde_result* out, kde_stream stream);
 
+/* --------------------------------------------------- no-allocation variant */
+
+/* kde_plugin_bandwidth_ex for callers that cannot allocate memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * It calls no hipMalloc, hipFree, hipHostMalloc or other allocating routine
+ * and no host synchronization; it only enqueues kernels on `stream`.
+ *   x, n, dtype: the sample, n >= 2, FP64 or FP32 (KDE_F64/KDE_F32), in device
+ *     memory on the context's GPU.
+ *   out: one kde_result in device-accessible memory (device memory on the
+ *     context's GPU, or pinned host memory from hipHostMalloc), written on
+ *     the stream.  Per-sample failures (KDE_ENONFINITE, KDE_EDEGENERATE,
+ *     KDE_ETIMEOUT) are reported in out->status, with out->h = NaN.
+ *   Asynchronous: the call returns once the work is enqueued; the caller
+ *   synchronizes the stream before reading out, and keeps x and out alive
+ *   until then.  The result is bitwise what kde_plugin_bandwidth_ex returns
+ *   for the same sample on the same context.  kde_ctx_last_device_ms and the
+ *   timeline are not updated.
+ *   Scratch: the work list, per-item partial sums, state and ticket live in a
+ *   static device array of KDE_NOALLOC_SCRATCH_BYTES (about 13 MiB) that each
+ *   GPU the library runs on holds once until the process ends; its address is
+ *   taken when the first context is created on the device.  Every call on a
+ *   GPU (from any context or thread) uses that one array, so calls whose work
+ *   overlaps on one GPU race: order them on one stream, or synchronize between
+ *   them.  Each call clears what must start at zero before it runs.
+ *   Limit: the work list of the sample (Step I chunks plus the pair items of
+ *   Steps IV and VI for the context's tile configuration) must fit in
+ *   KDE_NOALLOC_MAX_ITEMS items; the default configuration needs at most
+ *   about 209000 for any n.
+ *   Errors (returned, nothing enqueued): KDE_EINVAL (null pointer, n < 2,
+ *   bad dtype, x not device memory of the context's GPU, out not
+ *   device-accessible, work list over the limit), KDE_EDEVICE (a launch
+ *   failed, or the scratch is not set up on the device). */
+#define KDE_NOALLOC_MAX_ITEMS 262144
+#define KDE_NOALLOC_SCRATCH_BYTES 13634816
+KDE_API int kde_plugin_bandwidth_noalloc(kde_ctx* ctx, const void* x, int64_t n, int dtype,
+                                         kde_stream stream, kde_result* out);
+
 /* ---------------------------------------------- work decomposition / shards */
 
 /* Number of pair work items of one Psi stage for a sample of size n on this

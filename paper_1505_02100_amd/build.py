@@ -23,7 +23,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkdeplugin.so")
 
-SOURCES = ["kde_device.hip", "kde_eval.hip", "kde_host.cpp", "kde_tune.cpp", "kde_server.cpp"]
+SOURCES = ["kde_device.hip", "kde_eval.hip", "kde_host.cpp", "kde_tune.cpp", "kde_server.cpp",
+           "kde_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -524,6 +524,30 @@ int stage_x(kde_ctx* c, const void* x, int64_t n, int mem_kind, int dtype, hipSt
     return KDE_OK;
 }
 
+// Device-accessible address of out for the results kernel, or nullptr when out
+// is ordinary (pageable) host memory, which only the host can fill.
+kde_result* device_view(const kde_ctx* c, kde_result* out) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, out) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged)
+        return a.device == c->device ? out : nullptr;
+    if (a.type == hipMemoryTypeHost) return (kde_result*)(a.devicePointer ? a.devicePointer : (void*)out);
+    return nullptr;
+}
+
+// True when p points into memory on the context's GPU.
+bool on_device(const kde_ctx* c, const void* p) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == c->device;
+}
+
 int finish(kde_ctx* c, Plan& p, hipStream_t s) {
     (void)s;
     HIPCHK(hipEventSynchronize(c->ev1));
@@ -646,6 +670,11 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     HIPCHK(hipEventCreate(&c->ev1));
     int occ = 0;
     HIPCHK(persistent_occupancy(c->precision, c->R, &occ));
+    {
+        // device address of the static scratch of kde_plugin_bandwidth_noalloc
+        const int st = noalloc_init(c->device);
+        if (st) return st;
+    }
     c->blocks_per_cu = o.blocks_per_cu ? o.blocks_per_cu : (tt.bpc ? std::min(tt.bpc, std::max(1, occ)) : std::max(1, occ));
     *out = c.release();
     return ok();
@@ -749,20 +778,6 @@ int kde_plugin_bandwidth_ex(kde_ctx* c, const void* x, int64_t n, int mem_kind, 
         return set_err(out->status, "bandwidth selection failed on the device");
     }
     return ok();
-}
-
-// Device-accessible address of out for the results kernel, or nullptr when out
-// is ordinary (pageable) host memory, which only the host can fill.
-static kde_result* device_view(const kde_ctx* c, kde_result* out) {
-    hipPointerAttribute_t a{};
-    if (hipPointerGetAttributes(&a, out) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged)
-        return a.device == c->device ? out : nullptr;
-    if (a.type == hipMemoryTypeHost) return (kde_result*)(a.devicePointer ? a.devicePointer : (void*)out);
-    return nullptr;
 }
 
 int kde_plugin_bandwidth_batch(kde_ctx* c, const void* const* xs, const int64_t* ns, int64_t count,

@@ -154,5 +154,12 @@ void sample_items(const kde_ctx* c, int32_t ds, const Desc& d, const SampleSpec&
 // Fill the descriptor of one sample (everything but slot_base) and return the
 // number of slots it needs.
 int64_t describe_sample(const kde_ctx* c, const SampleSpec& ss, Desc* d);
+// Device-accessible address of a result buffer (device memory on the
+// context's GPU, or pinned host memory), or nullptr.
+kde_result* device_view(const kde_ctx* c, kde_result* out);
+bool on_device(const kde_ctx* c, const void* p);
+// Take the device address of the no-allocation scratch on `device` (once per
+// device; kde_ctx_create calls it).
+int noalloc_init(int device);
 }  // namespace rt
 }  // namespace kde

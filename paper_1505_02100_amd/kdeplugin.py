@@ -146,6 +146,7 @@ _sig("kde_plugin_bandwidth_ex", ctypes.c_int, _P, _P, _I64, ctypes.c_int, ctypes
      ctypes.POINTER(kde_result))
 _sig("kde_plugin_bandwidth_batch", ctypes.c_int, _P, ctypes.POINTER(_P), _PI64, _I64, ctypes.c_int,
      ctypes.POINTER(kde_result), _P)
+_sig("kde_plugin_bandwidth_noalloc", ctypes.c_int, _P, _P, _I64, ctypes.c_int, _P, ctypes.POINTER(kde_result))
 _sig("kde_ctx_last_timeline", ctypes.c_int, _P, _I64, ctypes.POINTER(_D))
 _sig("kde_ctx_last_device_ms", _D, _P)
 _sig("kde_psi_num_items", _I64, _P, _I64)
@@ -362,6 +363,27 @@ def kde_plugin_bandwidth_batch_async(ctx: int, xs: Sequence, out) -> None:
                                            ss[0].stream), "kde_plugin_bandwidth_batch")
 
 
+KDE_NOALLOC_MAX_ITEMS = 262144
+KDE_NOALLOC_SCRATCH_BYTES = 13634816
+
+
+def kde_plugin_bandwidth_noalloc(ctx: int, x, out) -> None:
+    """Enqueue one selection of the device sample ``x`` (torch CUDA float64 or
+    float32 tensor) on torch's current stream without any allocation by the
+    library; the kde_result lands in ``out`` (a torch tensor in device memory
+    or pinned host memory of at least sizeof(kde_result) bytes) when the
+    stream gets there.  Read it with ``batch_results(out, 1)[0]`` after
+    synchronizing the stream."""
+    s = _Samples(x)
+    if s.mem != KDE_MEM_DEVICE:
+        raise TypeError("kde_plugin_bandwidth_noalloc takes a torch CUDA tensor")
+    if out.numel() * out.element_size() < ctypes.sizeof(kde_result):
+        raise ValueError("output buffer too small")
+    _check(_lib.kde_plugin_bandwidth_noalloc(ctx, s.ptr, s.n, s.dtype, s.stream,
+                                             ctypes.cast(out.data_ptr(), ctypes.POINTER(kde_result))),
+           "kde_plugin_bandwidth_noalloc")
+
+
 def batch_results(out, count: int) -> List[kde_result]:
     """kde_result records from a buffer written by an asynchronous batch (after
     the caller has synchronized its stream)."""
@@ -531,6 +553,9 @@ class Context:
 
     def plugin_bandwidth_batch_async(self, xs: Iterable, out):
         return kde_plugin_bandwidth_batch_async(self.handle, list(xs), out)
+
+    def plugin_bandwidth_noalloc(self, x, out):
+        return kde_plugin_bandwidth_noalloc(self.handle, x, out)
 
     def psi_num_items(self, n):
         return kde_psi_num_items(self.handle, n)
