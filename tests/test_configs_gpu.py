@@ -3,20 +3,26 @@ configuration bench.py times (default context tile shape, one persistent
 launch per call, device-resident samples).
 
 * bimodal n = 65536: full oracle comparison, both precisions.
-* lognormal n = 2^20 (x = 1e3 exp(Z) - 5e2): the O(n^2) oracle would take
-  minutes, so sampled pair items are compared one by one with the oracle's
-  block sums over the same rectangles, and the whole result is checked
-  through properties that hold at any size (scale equivariance, agreement of
-  the FP32 and FP64 paths, sign invariant).
+* lognormal n = 2^20 (x = 1e3 exp(Z) - 5e2): every precision's sigma, Psi8,
+  g1, Psi6, g2, Psi4 and h against the oracle's stored record of the same
+  bytes (tests/golden/full_size_records.json, written by make_full_size.py
+  from the oracle alone, matched by SHA-256); sampled pair items one by one
+  against the oracle's block sums over the same rectangles; and properties
+  that hold at any size (scale equivariance, sign invariant).
 * the serving workload's largest request, n = 4*10^6 (Student t3): sampled
   pair items of both stages against the oracle's block sums, and properties
   (FP32 against exact-k FP32, scale equivariance, sign invariant).
 * batch of 512 samples, n log-uniform in [256, 65536], mixed distributions:
-  every h against the FP64 batch and against the oracle for all samples with
-  n <= 4096 plus a few larger ones; the batch results are bitwise those of
-  single calls.
+  all 512 results of every precision against the oracle's stored records;
+  the batch results are bitwise those of single calls.
+
+The Q32.32 emulation is held to the bound its own arithmetic gives, which
+the tests evaluate at n <= 4097 (test_parity_gpu.py); at these sizes that
+bound is not computed and the mode is not compared here.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -44,6 +50,30 @@ def ctxs(kp):
 
 def _rel(a, b):
     return abs(a - b) / abs(b)
+
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+with open(os.path.join(_HERE, "golden", "full_size_records.json")) as _f:
+    FULL = json.load(_f)
+
+# Tolerances against the FP64 oracle (relative): FP64 plain on both sides with
+# different summation orders; the FP32 precisions to the 1e-6 bound on h they
+# are built to, their Psi estimates to the bounds of the parity suite.  The
+# moment stage and Steps II-III are FP64 in every precision.
+TOL = {"FP64_PLAIN": dict(h=1e-12, psi6=1e-12, psi4=1e-12, g2=1e-12),
+       "FP32_COMP": dict(h=1e-6, psi6=1e-5, psi4=5e-6, g2=2e-6),
+       "FP32_COMP_EXACT": dict(h=1e-6, psi6=1e-5, psi4=5e-6, g2=2e-6),
+       "FP32_POLYEXP": dict(h=1e-6, psi6=1e-5, psi4=5e-6, g2=2e-6)}
+TOL_MOMENTS = dict(sigma=1e-13, psi8=1e-12, g1=1e-13)
+
+
+def _against_record(res, rec, prec, psi_scale=1.0, where=""):
+    want = {k: float.fromhex(v) for k, v in rec.items()}
+    assert res.status == 0, where
+    for k, t in list(TOL[prec].items()) + list(TOL_MOMENTS.items()):
+        if k in ("psi6", "psi4", "g2"):
+            t *= psi_scale
+        assert _rel(getattr(res, k), want[k]) <= t, (where, prec, k, getattr(res, k), want[k])
 
 
 def test_bimodal_65536_full_oracle(kp, ctxs):
@@ -81,6 +111,17 @@ def _abs_block_sum_uncached(x, r, g, r0, r1, c0, c1):
     return tot
 
 
+def test_lognormal_1m_against_the_oracle_record(kp, ctxs):
+    import torch
+    rec = FULL["lognormal1m"]
+    x = synth.workload_single_lognormal(1 << 20, 2)
+    assert synth.sha256(x) == rec["sha256"]
+    xd = torch.from_numpy(x).cuda()
+    for prec in TOL:
+        r = ctxs[getattr(kp, "KDE_" + prec)].plugin_bandwidth(xd)
+        _against_record(r, rec["plugin"], prec, where="lognormal n=2^20")
+
+
 def test_lognormal_1m_sampled_items_and_properties(kp, ctxs):
     import torch
     n = 1 << 20
@@ -90,6 +131,7 @@ def test_lognormal_1m_sampled_items_and_properties(kp, ctxs):
     xd = torch.from_numpy(x).cuda()
     r64 = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth(xd)
     assert r64.status == 0 and r64.psi6 < 0 < r64.psi4
+    assert r64.g1 == pytest.approx(float.fromhex(FULL["lognormal1m"]["plugin"]["g1"]), rel=1e-13)
     # sampled items of the Step IV stage at the FP64 path's g1, each against the oracle
     for p, eps in ((kp.KDE_FP64_PLAIN, 1e-13), (kp.KDE_FP32_COMP, 2e-6)):
         ctx = ctxs[p]
@@ -141,20 +183,26 @@ def batch512():
 
 def test_batch_512(kp, ctxs, batch512):
     import torch
-    xs, _ = batch512
+    xs, names = batch512
+    recs = FULL["batch512"]["samples"]
+    assert len(recs) == len(xs) == 512
+    for k, (x, nm) in enumerate(zip(xs, names)):
+        assert recs[k]["k"] == k and recs[k]["dist"] == nm and recs[k]["sha256"] == synth.sha256(x), k
     xds = [torch.from_numpy(x).cuda() for x in xs]
-    b64 = ctxs[kp.KDE_FP64_PLAIN].plugin_bandwidth_batch(xds)
-    b32 = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth_batch(xds)
-    assert all(r.status == 0 for r in b64) and all(r.status == 0 for r in b32)
-    worst = max(_rel(a.h, b.h) for a, b in zip(b32, b64))
-    assert worst < 1e-6, worst
-    # oracle on every small sample and a few large ones
-    idx = [k for k, x in enumerate(xs) if x.size <= 4096]
-    idx += sorted(np.argsort([-x.size for x in xs])[:2].tolist())
-    for k in idx:
+    out = {}
+    for prec in TOL:
+        out[prec] = ctxs[getattr(kp, "KDE_" + prec)].plugin_bandwidth_batch(xds)
+        # every sample against the oracle; the Psi bounds of the small-n parity
+        # suite (2e-5) for the FP32 precisions
+        scale = 1.0 if prec == "FP64_PLAIN" else 2.0
+        for k in range(len(xs)):
+            _against_record(out[prec][k], recs[k]["plugin"], prec, psi_scale=scale,
+                            where=f"batch sample {k} n={xs[k].size}")
+    b32 = out["FP32_COMP"]
+    # the oracle itself, run here on the smallest sample and the largest
+    for k in (int(np.argmin([x.size for x in xs])), int(np.argmax([x.size for x in xs]))):
         ref = oracle.plugin(xs[k])
-        assert _rel(b64[k].h, ref.h) < 1e-12, (k, xs[k].size)
-        assert _rel(b32[k].h, ref.h) < 1e-6, (k, xs[k].size)
+        assert ref.h == pytest.approx(float.fromhex(recs[k]["plugin"]["h"]), rel=1e-15, abs=0), k
     # a batch result is bitwise the single-call result (decomposition depends on n only)
     for k in (0, 1, 77, 311, 511):
         s = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth(xds[k])

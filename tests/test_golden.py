@@ -30,3 +30,28 @@ def test_golden_record(key):
     got = oracle.plugin(x)
     for k, hexval in rec["plugin"].items():
         assert getattr(got, k) == pytest.approx(float.fromhex(hexval), rel=1e-15, abs=0), k
+
+
+with open(os.path.join(HERE, "golden", "full_size_records.json")) as f:
+    FULL = json.load(f)
+
+
+def test_full_size_records_match_their_samples():
+    # the stored records were made from exactly these bytes
+    assert synth.sha256(synth.workload_single_bimodal(65536, 1)) == FULL["bimodal65536"]["sha256"]
+    assert synth.sha256(synth.workload_single_lognormal(1 << 20, 2)) == FULL["lognormal1m"]["sha256"]
+    xs, names = synth.workload_batch(512, 3)
+    recs = FULL["batch512"]["samples"]
+    assert [r["sha256"] for r in recs] == [synth.sha256(x) for x in xs]
+    assert [r["dist"] for r in recs] == names and [r["n"] for r in recs] == [x.size for x in xs]
+
+
+@pytest.mark.parametrize("j", range(5))
+def test_full_size_batch_records_reproduce(j):
+    # the oracle reproduces its stored record of the j-th batch sample with
+    # n <= 8192 (kept quick)
+    xs, _ = synth.workload_batch(512, 3)
+    k = [q for q, x in enumerate(xs) if x.size <= 8192][j]
+    got = oracle.plugin(xs[k])
+    for name, hexval in FULL["batch512"]["samples"][k]["plugin"].items():
+        assert getattr(got, name) == pytest.approx(float.fromhex(hexval), rel=1e-15, abs=0), name
