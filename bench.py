@@ -323,13 +323,46 @@ def bench_serve(args):
     print(json.dumps(out))
 
 
+def bench_issue_rate(args):
+    """Issue rates of the pair stages' instructions (paper_1505_02100_amd/probes/
+    issue_rate, built by build()): FP32 fma/mul/sub, v_exp_f32, and the Step IV
+    and Step VI per-pair sequences in register-only loops at 2, 3, 4 and 8 waves
+    per SIMD, with the shader clock measured under that load.  The pair
+    sequences' rates are the ceiling of the pair kernels' instruction mix."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1505_02100_amd", "probes", "issue_rate")
+    if not os.path.exists(exe):
+        raise SystemExit(f"{exe} is not built: run __graft_entry__.build()")
+    r = subprocess.run([exe], capture_output=True, text=True, check=True)
+    probe = json.loads(r.stdout)
+    res = probe["results"]
+    best = {}
+    for row in res:
+        if row["op"] not in best or row["lane_steps_per_s"] > best[row["op"]]["lane_steps_per_s"]:
+            best[row["op"]] = row
+    pair = (best["pair_r6"]["lane_steps_per_s"] + best["pair_r4"]["lane_steps_per_s"]) / 2
+    tflops = sum(FLOP_PER_PAIR.values()) / 2 * pair / 1e12
+    out = {"metric": "issue rates of the pair-stage instruction mix (microbenchmark)",
+           "value": pair, "unit": "pair-evals/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "register-only loops of the Step IV / Step VI per-pair sequences and of "
+                                  "single FP32 instructions, 8 independent chains per lane"},
+           "pair_mix_ceiling": {"pair_evals_per_s": pair, "tflops_algorithmic": round(tflops, 2),
+                                "frac_of_157_3": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)},
+           "best_by_op": {k: {q: v[q] for q in ("waves_per_simd", "lane_insts_per_s", "insts_per_cu_cycle",
+                                                "sclk_mhz")} for k, v in best.items()},
+           "probe": probe}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["fp32", "fp32x", "fp32poly", "q32", "fp64"], default="fp32")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch512", "serve", "eval4096"],
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch512", "serve", "eval4096", "issue-rate"],
                     default="lognormal1m")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window in seconds")
@@ -363,6 +396,9 @@ def main():
         return
     if args.workload == "eval4096":
         bench_eval(args)
+        return
+    if args.workload == "issue-rate":
+        bench_issue_rate(args)
         return
 
     from paper_1505_02100_amd import kdeplugin as kp

@@ -68,5 +68,25 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+PROBE_SRC = os.path.join(HERE, "probes", "issue_rate.hip")
+PROBE = os.path.join(HERE, "probes", "issue_rate")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The issue-rate microbenchmark (a standalone HIP program, run by
+    bench.py --workload issue-rate)."""
+    tmp = PROBE + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Wall",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-o", tmp, PROBE_SRC]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE)
+    return PROBE
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_probe(verbose=True))
