@@ -312,15 +312,22 @@ KDE_API int kde_eval(const double* x, int64_t n, const double* y, int64_t m, dou
  * at any time; the server admits them (first come first served, or smallest
  * n first) into at most max_active slots against a device-memory budget,
  * keeps admitted samples resident on the device, and runs steps.  A step is
- * one launch of the persistent kernel over the next work items of every
- * active request, taken round-robin up to step_pairs pair evaluations
- * (processor sharing), so a request that arrives while others run joins at
- * the next step and its work overlaps theirs on the device.  Each result is
+ * one launch of the persistent kernel over the next work items of the
+ * active requests up to step_pairs pair evaluations, taken round-robin
+ * (processor sharing, the default) or in priority order (KDE_FILL_PRIORITY),
+ * so a request that arrives while others run joins at the next step and its
+ * work overlaps theirs on the device.  Each result is
  * bitwise what kde_plugin_bandwidth_ex returns for the same sample on the
  * same context.  Steps are queued two deep on the server's own stream.
  * A server uses its context exclusively; neither is thread-safe. */
 #define KDE_SERVE_FCFS 0
 #define KDE_SERVE_SJF 1
+/* How a step's pair budget is shared among the active requests: */
+#define KDE_FILL_SHARE 0    /* round-robin, one pair item per request per turn (processor sharing) */
+#define KDE_FILL_PRIORITY 1 /* in admission-key order (FCFS: oldest first; SJF: fewest remaining
+                               pair evaluations first, with the same aging), each request taking
+                               all it can before the next: finishes requests instead of spreading
+                               the device over all of them                                       */
 
 typedef struct kde_server kde_server;
 
@@ -330,6 +337,11 @@ typedef struct {
     int64_t step_pairs;  /* pair evaluations per step across all requests (default 2^34)     */
     int32_t max_active;  /* requests on the device at once (default 64)                       */
     int32_t policy;      /* KDE_SERVE_FCFS (default) or KDE_SERVE_SJF admission order         */
+    int64_t aging_ms;    /* KDE_SERVE_SJF: a queued request's key is log2 of its pair count
+                            minus one per aging_ms of waiting, so large requests overtake newer
+                            small ones instead of starving; 0 = pure smallest first (default)  */
+    int32_t fill;        /* KDE_FILL_SHARE (default) or KDE_FILL_PRIORITY                     */
+    int32_t reserved;
 } kde_server_options;
 
 typedef struct {
@@ -342,7 +354,8 @@ typedef struct {
 } kde_completion;
 
 typedef struct {
-    int32_t active, queued, inflight_steps, reserved;
+    int32_t active, queued, inflight_steps;
+    int32_t failed_steps;  /* steps that could not run (their requests completed with an error) */
     int64_t steps, arena_used, completed_unread;  /* arena_used: bytes counted against the budget */
     double pairs_done;   /* n(n-1) summed over completed requests                             */
     double pairs_issued; /* pair evaluations (i < j) of every item launched so far           */
@@ -368,6 +381,17 @@ KDE_API int kde_server_step(kde_server* srv, int32_t block, kde_server_stats* st
 KDE_API int kde_server_poll(kde_server* srv, kde_completion* out, int32_t max, int32_t* got);
 /* Step until every submitted request has finished. */
 KDE_API int kde_server_drain(kde_server* srv);
+
+/* Failure handling.  A step that cannot run (its kernel launch fails) fails
+ * the requests it lists: each completes with that status (h = NaN) once no
+ * earlier step still in flight can write its memory, and its slot and memory
+ * are freed; the other requests are unaffected and complete as usual.
+ * (Per-request failures found on the device -- KDE_ENONFINITE,
+ * KDE_EDEGENERATE, KDE_ETIMEOUT -- are reported in that request's result.)
+ * kde_server_fail_next_step makes the next step that has work fail with
+ * `code` (a negative KDE_E* value) without launching it, for tests of this
+ * path; KDE_EINVAL for a non-negative code. */
+KDE_API int kde_server_fail_next_step(kde_server* srv, int32_t code);
 
 /* ------------------------------------------------------------- autotuner */
 

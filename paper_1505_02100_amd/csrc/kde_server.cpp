@@ -19,6 +19,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -96,6 +98,9 @@ struct Request {
     hipEvent_t copied = nullptr;      // sample copy done (host samples)
     bool wait_copy = false;
     int64_t last_step = -1;           // sequence number of the step that listed its last items
+    int64_t launched_step = -1;       // sequence number of the last launched step listing any of its items
+    double listed_pairs = 0;          // pair evaluations of the items listed so far
+    int32_t fail = 0;                 // KDE_E* code once a step listing its items failed to run
 };
 
 struct Step {
@@ -129,6 +134,8 @@ struct kde_server {
     int64_t steps = 0;
     size_t device_sample_bytes = 0;   // admitted samples that live in caller memory
     double pairs_issued = 0;          // pair evaluations of all launched items
+    int32_t fail_next = 0;            // injected failure of the next step (kde_server_fail_next_step)
+    int32_t failed_steps = 0;
 };
 
 namespace {
@@ -192,13 +199,31 @@ int admit_one(kde_server* s, std::unique_ptr<Request>& rp) {
     return KDE_OK;
 }
 
+// Admission key of smallest-first: log2 of the request's pair count, minus
+// one for every aging_ms it has waited, so a large request overtakes newer
+// small ones after waiting (aging_ms = 0: no aging, pure smallest-first).
+double sjf_key(const kde_server* s, const Request& r, double now) {
+    double k = std::log2(std::max(1.0, r.pairs));
+    if (s->opt.aging_ms > 0) k -= (now - r.t_submit) / (double)s->opt.aging_ms;
+    return k;
+}
+
+// The same key on the pair evaluations a request still has to list (the
+// priority fill order of a step).
+double remaining_key(const kde_server* s, const Request& r, double now) {
+    double k = std::log2(std::max(1.0, r.pairs - r.listed_pairs));
+    if (s->opt.aging_ms > 0) k -= (now - r.t_submit) / (double)s->opt.aging_ms;
+    return k;
+}
+
 int admit(kde_server* s) {
+    const double now = now_ms();
     while (!s->queue.empty() && !s->free_slots.empty()) {
         auto pick = s->queue.begin();
         if (s->opt.policy == KDE_SERVE_SJF)
             pick = std::min_element(s->queue.begin(), s->queue.end(),
-                                    [](const std::unique_ptr<Request>& a, const std::unique_ptr<Request>& b) {
-                                        return a->n < b->n;
+                                    [&](const std::unique_ptr<Request>& a, const std::unique_ptr<Request>& b) {
+                                        return sjf_key(s, *a, now) < sjf_key(s, *b, now);
                                     });
         const int st = admit_one(s, *pick);
         if (st == KDE_ENOMEM) break;  // wait for memory to free up
@@ -259,14 +284,16 @@ int launch_step(kde_server* s) {
     const size_t m = s->active.size();
     std::vector<bool> exhausted(m, false);
     size_t left = m;
+    std::vector<bool> listed(m, false);
     for (size_t k = 0; k < m; ++k)
-        if (s->active[k]->stage >= NUM_STAGES) {
+        if (s->active[k]->stage >= NUM_STAGES || s->active[k]->fail) {
             exhausted[k] = true;
             --left;
         }
-    // round-robin, one pair item per request per turn; moment items ride free.
+    double step_pairs = 0.0;
     // A request's cursor always points at its next unlisted item; when the last
-    // one is listed, last_step records the step being built.
+    // one is listed, last_step records the step being built.  Moment items
+    // ride free (they count no pairs).
     auto advance = [](Request& r) {
         while (r.stage < NUM_STAGES && r.next >= r.desc.n_items[r.stage]) {
             ++r.stage;
@@ -274,27 +301,55 @@ int launch_step(kde_server* s) {
             r.rb = r.cb = 0;
         }
     };
-    size_t turn = s->rr % std::max<size_t>(1, m);
-    while (left > 0 && budget > 0) {
-        for (size_t q = 0; q < m && budget > 0; ++q) {
-            const size_t k = (turn + q) % m;
-            if (exhausted[k]) continue;
-            Request& r = *s->active[k];
-            for (;;) {
-                advance(r);
-                if (r.stage >= NUM_STAGES) break;
-                const Item it = next_item(r);
-                stage_lists[it.stage].push_back(it);
-                const double p = item_pairs(r, it);
-                budget -= p;
-                s->pairs_issued += p;
-                if (p > 0) break;  // one pair item per turn
-            }
+    // List the next items of active request k up to `max_pair_items` pair
+    // items (or until the budget runs out); true once it has none left.
+    auto take = [&](size_t k, int64_t max_pair_items) {
+        Request& r = *s->active[k];
+        int64_t got = 0;
+        for (;;) {
             advance(r);
-            if (r.stage >= NUM_STAGES) {
-                exhausted[k] = true;
-                --left;
-                r.last_step = s->steps;  // the step being built
+            if (r.stage >= NUM_STAGES || got >= max_pair_items || budget <= 0) break;
+            const Item it = next_item(r);
+            stage_lists[it.stage].push_back(it);
+            listed[k] = true;
+            const double p = item_pairs(r, it);
+            budget -= p;
+            step_pairs += p;
+            r.listed_pairs += p;
+            if (p > 0) ++got;
+        }
+        if (r.stage >= NUM_STAGES) {
+            exhausted[k] = true;
+            --left;
+            r.last_step = s->steps;  // the step being built
+            return true;
+        }
+        return false;
+    };
+    if (s->opt.fill == KDE_FILL_PRIORITY) {
+        // the budget goes to the requests in admission-key order, each taking
+        // as much as it can use before the next one gets any
+        std::vector<size_t> order;
+        for (size_t k = 0; k < m; ++k)
+            if (!exhausted[k]) order.push_back(k);
+        const double now = now_ms();
+        std::vector<double> key(m, 0.0);
+        for (size_t k : order) {
+            const Request& r = *s->active[k];
+            key[k] = s->opt.policy == KDE_SERVE_SJF ? remaining_key(s, r, now) : (double)r.id;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return key[a] < key[b]; });
+        for (size_t k : order) {
+            if (budget <= 0) break;
+            take(k, INT64_MAX);
+        }
+    } else {
+        // round-robin, one pair item per request per turn (processor sharing)
+        const size_t turn = s->rr % std::max<size_t>(1, m);
+        while (left > 0 && budget > 0) {
+            for (size_t q = 0; q < m && budget > 0; ++q) {
+                const size_t k = (turn + q) % m;
+                if (!exhausted[k]) take(k, 1);
             }
         }
     }
@@ -302,6 +357,22 @@ int launch_step(kde_server* s) {
     size_t total = 0;
     for (auto& v : stage_lists) total += v.size();
     if (total == 0) return KDE_OK;
+    // A step that cannot run (its launch failed, or a failure injected for
+    // tests) fails the requests it lists: their device state misses these
+    // items, so they complete with the failure once no earlier step can still
+    // write their memory; the other requests go on.
+    auto fail_step = [&](int32_t code) {
+        for (size_t k = 0; k < m; ++k)
+            if (listed[k] && !s->active[k]->fail) s->active[k]->fail = code;
+        ++s->failed_steps;
+        ++s->steps;
+        return KDE_OK;
+    };
+    if (s->fail_next) {
+        const int32_t code = s->fail_next;
+        s->fail_next = 0;
+        return fail_step(code);
+    }
     // the compute stream waits for sample copies of newly listed requests
     for (auto& rp : s->active)
         if (rp->wait_copy) {
@@ -342,7 +413,14 @@ int launch_step(kde_server* s) {
     a.ticket = ticket;
     a.pc = s->ctx->pc;
     a.timeout_ticks = kTimeoutTicks;
-    HIPCHK(launch_persistent(s->ctx->precision, s->ctx->R, step_grid(s->ctx, (int64_t)total), s->stream, a));
+    if (launch_persistent(s->ctx->precision, s->ctx->R, step_grid(s->ctx, (int64_t)total), s->stream, a) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return fail_step(KDE_EDEVICE);
+    }
+    for (size_t k = 0; k < m; ++k)
+        if (listed[k]) s->active[k]->launched_step = s->steps;
+    s->pairs_issued += step_pairs;
     HIPCHK(hipMemcpyAsync(s->h_states[b], s->d_states.p, sizeof(State) * (size_t)s->opt.max_active,
                           hipMemcpyDeviceToHost, s->stream));
     Step st;
@@ -353,6 +431,23 @@ int launch_step(kde_server* s) {
     s->inflight.push_back(st);
     ++s->steps;
     return KDE_OK;
+}
+
+// Hand active request k to the caller with result c and free its slot,
+// arena block and budget.
+void complete(kde_server* s, size_t k, kde_completion c, double t) {
+    Request& r = *s->active[k];
+    c.id = r.id;
+    c.n = r.n;
+    c.t_submit_ms = r.t_submit;
+    c.t_admit_ms = r.t_admit;
+    c.t_done_ms = t;
+    s->done.push_back(c);
+    s->arena->release(r.off, r.bytes);
+    if (r.mem_kind == KDE_MEM_DEVICE) s->device_sample_bytes -= (size_t)r.n * sizeof(double);
+    s->free_slots.push_back(r.slot);
+    if (r.copied) (void)hipEventDestroy(r.copied);
+    s->active.erase(s->active.begin() + (long)k);
 }
 
 // Retire the oldest step and collect the requests whose last stage has
@@ -377,27 +472,34 @@ int retire_step(kde_server* s, bool block) {
         // only a read-back taken after the step that listed the request's last
         // items can show its final flag (older ones may still hold the state of
         // the slot's previous request)
-        if (r.stage >= NUM_STAGES && r.last_step >= 0 && st.seq >= r.last_step && h.ready[ST_PSI4]) {
+        if (!r.fail && r.stage >= NUM_STAGES && r.last_step >= 0 && st.seq >= r.last_step && h.ready[ST_PSI4]) {
             kde_completion c{};
-            c.id = r.id;
             fill_result(h, &c.result);
             if (c.result.status) c.result.h = NAN;
-            c.n = r.n;
-            c.t_submit_ms = r.t_submit;
-            c.t_admit_ms = r.t_admit;
-            c.t_done_ms = t;
-            s->done.push_back(c);
+            complete(s, k, c, t);
             s->pairs_done += r.pairs;
-            s->arena->release(r.off, r.bytes);
-            if (r.mem_kind == KDE_MEM_DEVICE) s->device_sample_bytes -= (size_t)r.n * sizeof(double);
-            s->free_slots.push_back(r.slot);
-            if (r.copied) (void)hipEventDestroy(r.copied);
-            s->active.erase(s->active.begin() + (long)k);
         } else {
             ++k;
         }
     }
     return KDE_OK;
+}
+
+// Complete the failed requests that no step in flight can still touch.
+void reap_failed(kde_server* s) {
+    const int64_t oldest = s->inflight.empty() ? INT64_MAX : s->inflight.front().seq;
+    const double t = now_ms();
+    for (size_t k = 0; k < s->active.size();) {
+        Request& r = *s->active[k];
+        if (r.fail && r.launched_step < oldest) {
+            kde_completion c{};
+            c.result.h = NAN;
+            c.result.status = r.fail;
+            complete(s, k, c, t);
+        } else {
+            ++k;
+        }
+    }
 }
 
 }  // namespace
@@ -411,6 +513,8 @@ void kde_server_options_init(kde_server_options* o) {
     o->max_active = 64;
     o->step_pairs = (int64_t)1 << 34;
     o->policy = KDE_SERVE_FCFS;
+    o->aging_ms = 0;
+    o->fill = KDE_FILL_SHARE;
 }
 
 int kde_server_create(kde_server** out, kde_ctx* ctx, const kde_server_options* opt) {
@@ -420,7 +524,8 @@ int kde_server_create(kde_server** out, kde_ctx* ctx, const kde_server_options* 
     kde_server_options_init(&o);
     if (opt) o = *opt;
     if (o.mem_budget < ((int64_t)1 << 20) || o.max_active < 1 || o.max_active > 65536 || o.step_pairs < 1 ||
-        (o.policy != KDE_SERVE_FCFS && o.policy != KDE_SERVE_SJF))
+        (o.policy != KDE_SERVE_FCFS && o.policy != KDE_SERVE_SJF) || o.aging_ms < 0 ||
+        (o.fill != KDE_FILL_SHARE && o.fill != KDE_FILL_PRIORITY))
         return set_err(KDE_EINVAL, "bad server options");
     DeviceGuard dg(ctx->device);
     auto s = std::make_unique<kde_server>();
@@ -511,6 +616,7 @@ int kde_server_step(kde_server* s, int32_t block, kde_server_stats* stats) {
         if (st) return st;
     }
     if (s->inflight.size() >= 2 && block && (st = retire_step(s, true))) return st;
+    reap_failed(s);
     if ((st = admit(s))) return st;
     const int64_t before = s->steps;
     if (s->inflight.size() < 2 && (st = launch_step(s))) return st;
@@ -518,6 +624,7 @@ int kde_server_step(kde_server* s, int32_t block, kde_server_stats* stats) {
     // the oldest step, then admit into whatever it freed and launch again
     if (block && s->steps == before && !s->inflight.empty()) {
         if ((st = retire_step(s, true))) return st;
+        reap_failed(s);
         if ((st = admit(s))) return st;
         if (s->inflight.size() < 2 && (st = launch_step(s))) return st;
     }
@@ -525,6 +632,7 @@ int kde_server_step(kde_server* s, int32_t block, kde_server_stats* stats) {
         stats->active = (int32_t)s->active.size();
         stats->queued = (int32_t)s->queue.size();
         stats->inflight_steps = (int32_t)s->inflight.size();
+        stats->failed_steps = s->failed_steps;
         stats->steps = s->steps;
         stats->arena_used = (int64_t)(s->arena->used() + s->device_sample_bytes);
         stats->pairs_done = s->pairs_done;
@@ -540,6 +648,12 @@ int kde_server_poll(kde_server* s, kde_completion* out, int32_t max, int32_t* go
     for (int32_t q = 0; q < k; ++q) out[q] = s->done[(size_t)q];
     s->done.erase(s->done.begin(), s->done.begin() + k);
     *got = k;
+    return ok();
+}
+
+int kde_server_fail_next_step(kde_server* s, int32_t code) {
+    if (!s || code >= 0) return set_err(KDE_EINVAL, "null server or non-negative failure code");
+    s->fail_next = code;
     return ok();
 }
 

@@ -87,7 +87,8 @@ class kde_result(ctypes.Structure):
 
 class kde_server_options(ctypes.Structure):
     _fields_ = [("mem_budget", ctypes.c_int64), ("step_pairs", ctypes.c_int64),
-                ("max_active", ctypes.c_int32), ("policy", ctypes.c_int32)]
+                ("max_active", ctypes.c_int32), ("policy", ctypes.c_int32),
+                ("aging_ms", ctypes.c_int64), ("fill", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class kde_completion(ctypes.Structure):
@@ -98,7 +99,7 @@ class kde_completion(ctypes.Structure):
 
 class kde_server_stats(ctypes.Structure):
     _fields_ = [("active", ctypes.c_int32), ("queued", ctypes.c_int32),
-                ("inflight_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("inflight_steps", ctypes.c_int32), ("failed_steps", ctypes.c_int32),
                 ("steps", ctypes.c_int64), ("arena_used", ctypes.c_int64),
                 ("completed_unread", ctypes.c_int64), ("pairs_done", ctypes.c_double),
                 ("pairs_issued", ctypes.c_double)]
@@ -106,6 +107,8 @@ class kde_server_stats(ctypes.Structure):
 
 KDE_SERVE_FCFS = 0
 KDE_SERVE_SJF = 1
+KDE_FILL_SHARE = 0
+KDE_FILL_PRIORITY = 1
 
 
 class KdeError(RuntimeError):
@@ -158,6 +161,7 @@ _sig("kde_server_cancel", ctypes.c_int, _P, _I64)
 _sig("kde_server_step", ctypes.c_int, _P, _I32, ctypes.POINTER(kde_server_stats))
 _sig("kde_server_poll", ctypes.c_int, _P, ctypes.POINTER(kde_completion), _I32, _PI32)
 _sig("kde_server_drain", ctypes.c_int, _P)
+_sig("kde_server_fail_next_step", ctypes.c_int, _P, _I32)
 _sig("kde_autotune", ctypes.c_int, ctypes.POINTER(kde_options), _PI64, _I32, _I32, _I32, ctypes.c_char_p,
      _I32)
 _sig("kde_psi_item_geometry", ctypes.c_int, _P, _I64, _I64, _PI64, _PI64, _PI64, _PI64)
@@ -489,6 +493,10 @@ def kde_server_poll(srv: int, max_items: int = 4096) -> List[kde_completion]:
 
 def kde_server_drain(srv: int) -> None:
     _check(_lib.kde_server_drain(srv), "kde_server_drain")
+
+
+def kde_server_fail_next_step(srv: int, code: int) -> None:
+    _check(_lib.kde_server_fail_next_step(srv, int(code)), "kde_server_fail_next_step")
 
 
 KDE_TUNE_SINGLE = 0
