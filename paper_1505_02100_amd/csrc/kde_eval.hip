@@ -7,19 +7,26 @@
 // (one point per thread) and the n samples into chunks of W columns; a
 // block evaluates one (tile, chunk) item, streaming its chunk through LDS in
 // tiles of TJ values read as b128 broadcasts, and writes one partial sum per
-// point.  A second kernel adds a point's partials in chunk order (so results
+// point.  A second kernel adds a point's partials in a fixed order (so results
 // are deterministic) and applies the normalisation 1 / (n h sqrt(2 pi)).
 //
 // FP32 arithmetic.  With k = log2(e)/2 and s = sqrt(k) / h, the scaled
 // values v = (x - c) s (computed in FP64, then rounded) give
-//     phi-factor exp(-((y - x)/h)^2 / 2) = 2^(-(v_y - v_x)^2),
-// so a pair costs a subtraction, a square, one v_exp_f32 and an add.  The
-// centre c is the midrange of the tile's points, so the rounding of v_y and
-// of the columns that matter (within a few bandwidths of the tile) stays at
-// a few ulp of small numbers.  A tile whose points spread over more than
-// kEvalSpan scaled units takes the difference y - x in FP64 instead (then
-// squares it in FP64 and rounds once before the exp2); this is the case for
-// unsorted evaluation points.  Each point keeps four FP32 accumulators that
+//     phi-factor exp(-((y - x)/h)^2 / 2) = 2^(-(v_y - v_x)^2)
+//                                        = 2^(-v_y^2) 2^(v_x (2 v_y) - v_x^2),
+// so with (v_x, -v_x^2) stored per column a pair costs one fma, one
+// v_exp_f32 and an add, and each point's sum is scaled by 2^(-v_y^2) once.
+// The exponent v_y^2 - (v_y - v_x)^2 never exceeds v_y^2, so nothing
+// overflows, and far columns underflow to 0 as they should.  Each
+// group of 32 points (half a wave) has its own centre c, the midrange of its
+// points, and its own FP32 copy of the column tile in LDS, centred on it: the
+// rounding of v_y and of the columns that matter (within a few bandwidths of
+// the group) then stays at a few ulp of small numbers.  A block with a group
+// whose points spread over more than kEvalSpan scaled units (about 9.4 h)
+// takes the difference y - x in FP64 instead (then squares it in FP64 and
+// rounds once before the exp2); this is the case for unsorted evaluation
+// points.  Sorted points and grids up to a spacing of about 0.3 h take the
+// FP32 path.  Each point keeps four FP32 accumulators that
 // take at most kEvalFold terms each, adds them pairwise in FP32 and folds
 // the result into an FP64 sum.  There is no cancellation (every term is
 // positive), so the relative error per point is that of the terms: a few
@@ -37,7 +44,10 @@ namespace kde {
 namespace eval {
 
 constexpr int BLOCK = 256;
-constexpr int TJ = 1024;        // column values per LDS tile
+constexpr int TJ = 1024;        // column values per LDS tile (FP64 paths)
+constexpr int GROUP = 32;       // points sharing a centre (FP32 path)
+constexpr int NGROUP = BLOCK / GROUP;
+constexpr int TJN = 256;        // columns per LDS tile and group (FP32 path; two floats each)
 constexpr int kEvalFold = 4;    // b128 reads per FP32 accumulator before the FP64 fold
 constexpr double kEvalSpan = 8.0;
 
@@ -76,8 +86,14 @@ __device__ __forceinline__ void flag_nonfinite(int32_t* flag) {
 // differences for a wide tile).
 template <int PREC>
 __global__ __launch_bounds__(BLOCK) void k_eval(EvalArgs a) {
-    __shared__ __align__(16) double tile64[TJ];
+    // FP64 plain: one FP64 tile; FP32: NGROUP FP32 tiles of TJN, or (wide
+    // blocks) one FP64 tile of TJ in the same memory
+    constexpr int kLdsDoubles = PREC == 0 ? TJ : NGROUP * TJN;
+    static_assert(PREC == 0 || kLdsDoubles >= TJ, "the FP64 tile fits the group tiles");
+    __shared__ __align__(16) double tile64[kLdsDoubles];
     __shared__ double red[2 * BLOCK / 64];
+    __shared__ double gcen[NGROUP];
+    __shared__ int32_t gwide;
     float* tile32 = reinterpret_cast<float*>(tile64);
 
     const int tid = threadIdx.x;
@@ -120,51 +136,94 @@ __global__ __launch_bounds__(BLOCK) void k_eval(EvalArgs a) {
             }
         }
     } else {
-        // centre and spread of this tile's points
-        double hi;
-        const double lo = block_min_max(live ? y : INFINITY, live ? y : -INFINITY, red, &hi);
-        const double c = 0.5 * lo + 0.5 * hi;
-        const bool narrow = (hi - lo) * a.s <= kEvalSpan;
-        const float vy = (float)((y - c) * a.s);
-        const double uy = (y - c) * a.s;
+        // centre and spread of each group of 32 points (lanes 0-31 and 32-63
+        // of a wave); a group without live points is narrow
+        double glo = live ? y : INFINITY, ghi = live ? y : -INFINITY;
+#pragma unroll
+        for (int off = GROUP / 2; off > 0; off >>= 1) {
+            glo = fmin(glo, __shfl_xor(glo, off, 64));
+            ghi = fmax(ghi, __shfl_xor(ghi, off, 64));
+        }
+        const int grp = tid / GROUP;
+        if (tid == 0) gwide = 0;
+        __syncthreads();
+        if ((tid & (GROUP - 1)) == 0) {
+            const bool any = glo <= ghi;
+            gcen[grp] = any ? 0.5 * glo + 0.5 * ghi : 0.0;
+            if (any && (ghi - glo) * a.s > kEvalSpan) atomicOr(&gwide, 1);
+        }
+        __syncthreads();
+        const bool narrow = gwide == 0;
         float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int64_t cj = c0; cj < c1; cj += TJ) {
-            const int len = (int)min((int64_t)TJ, c1 - cj);
-            __syncthreads();
-            for (int e = tid; e < TJ; e += BLOCK) {
-                double v = INFINITY;
-                if (e < len) {
-                    v = load_x(a.x, a.dtype, cj + e);
-                    if (!isfinite(v)) {
-                        flag_nonfinite(a.flag);
-                        v = INFINITY;
-                    } else {
-                        v = (v - c) * a.s;
+        if (narrow) {
+            // 2^(-(v_y - v_x)^2) = 2^(-v_y^2) 2^(fma(v_x, 2 v_y, -v_x^2)): the
+            // column tile holds (v_x, -v_x^2), the argument is at most v_y^2
+            // (<= 16 here), and the point's factor 2^(-v_y^2) is applied once
+            // at the end in FP64, so a pair costs an fma, the exp2 and an add
+            const float vy = (float)((y - gcen[grp]) * a.s);
+            const float vy2 = 2.0f * vy;
+            float2* tile2 = reinterpret_cast<float2*>(tile64);
+            const float4* t4 = reinterpret_cast<const float4*>(tile2 + grp * TJN);
+            for (int64_t cj = c0; cj < c1; cj += TJN) {
+                const int len = (int)min((int64_t)TJN, c1 - cj);
+                __syncthreads();
+                for (int e = tid; e < TJN; e += BLOCK) {
+                    double v = 0.0;
+                    bool pad = true;
+                    if (e < len) {
+                        v = load_x(a.x, a.dtype, cj + e);
+                        if (!isfinite(v))
+                            flag_nonfinite(a.flag);
+                        else
+                            pad = false;
+                    }
+#pragma unroll
+                    for (int g = 0; g < NGROUP; ++g) {
+                        // a column too far away for v_x^2 to stay finite contributes 0
+                        const double vxd = (v - gcen[g]) * a.s;
+                        const bool zero = pad || !(fabs(vxd) < 1e15);
+                        const float vx = zero ? 0.0f : (float)vxd;
+                        tile2[g * TJN + e] = make_float2(vx, zero ? -INFINITY : -(vx * vx));
                     }
                 }
-                if (narrow)
-                    tile32[e] = (float)v;
-                else
-                    tile64[e] = v;
-            }
-            __syncthreads();
-            const int groups = (len + 4 * kEvalFold - 1) / (4 * kEvalFold);
-            if (narrow) {
-                const float4* t4 = reinterpret_cast<const float4*>(tile32);
+                __syncthreads();
+                const int groups = (len + 4 * kEvalFold - 1) / (4 * kEvalFold);
                 for (int g = 0; g < groups; ++g) {
 #pragma unroll
-                    for (int q = 0; q < kEvalFold; ++q) {
-                        const float4 v = t4[g * kEvalFold + q];
-                        const float d0 = vy - v.x, d1 = vy - v.y, d2 = vy - v.z, d3 = vy - v.w;
-                        acc[0] += __builtin_amdgcn_exp2f(-(d0 * d0));
-                        acc[1] += __builtin_amdgcn_exp2f(-(d1 * d1));
-                        acc[2] += __builtin_amdgcn_exp2f(-(d2 * d2));
-                        acc[3] += __builtin_amdgcn_exp2f(-(d3 * d3));
+                    for (int q = 0; q < 2 * kEvalFold; ++q) {
+                        const float4 v = t4[g * 2 * kEvalFold + q];
+                        acc[(2 * q) & 3] += __builtin_amdgcn_exp2f(__builtin_fmaf(v.x, vy2, v.y));
+                        acc[(2 * q + 1) & 3] += __builtin_amdgcn_exp2f(__builtin_fmaf(v.z, vy2, v.w));
                     }
                     tot += (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
                     acc[0] = acc[1] = acc[2] = acc[3] = 0.0f;
                 }
-            } else {
+            }
+            tot *= exp2(-((double)vy * (double)vy));
+        } else {
+            // one centre for the block, differences in FP64
+            double hi;
+            const double lo = block_min_max(live ? y : INFINITY, live ? y : -INFINITY, red, &hi);
+            const double c = 0.5 * lo + 0.5 * hi;
+            const double uy = (y - c) * a.s;
+            for (int64_t cj = c0; cj < c1; cj += TJ) {
+                const int len = (int)min((int64_t)TJ, c1 - cj);
+                __syncthreads();
+                for (int e = tid; e < TJ; e += BLOCK) {
+                    double v = INFINITY;
+                    if (e < len) {
+                        v = load_x(a.x, a.dtype, cj + e);
+                        if (!isfinite(v)) {
+                            flag_nonfinite(a.flag);
+                            v = INFINITY;
+                        } else {
+                            v = (v - c) * a.s;
+                        }
+                    }
+                    tile64[e] = v;
+                }
+                __syncthreads();
+                const int groups = (len + 4 * kEvalFold - 1) / (4 * kEvalFold);
                 const double2* t2 = reinterpret_cast<const double2*>(tile64);
                 for (int g = 0; g < groups; ++g) {
 #pragma unroll
@@ -188,14 +247,30 @@ __global__ __launch_bounds__(BLOCK) void k_eval(EvalArgs a) {
     }
 }
 
-// out[k] = norm * sum over chunks, in chunk order.
+// out[k] = norm * sum over chunks in a fixed order: RLANES threads per point,
+// lane q adding chunks q, q + RLANES, q + 2 RLANES, ... in order, then lane 0
+// adding the RLANES lane sums in lane order (deterministic).  Consecutive
+// threads take consecutive points, so each load instruction reads whole
+// lines of one chunk's partials.
+constexpr int RLANES = 16;
+constexpr int RPOINTS = BLOCK / RLANES;
+
 __global__ __launch_bounds__(BLOCK) void k_eval_reduce(const double* part, int32_t n_cc, int64_t m, double norm,
                                                        double* out) {
-    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (k >= m) return;
+    __shared__ double red[RLANES][RPOINTS];
+    const int p = threadIdx.x % RPOINTS, q = threadIdx.x / RPOINTS;
+    const int64_t k = (int64_t)blockIdx.x * RPOINTS + p;
     double s = 0.0;
-    for (int32_t c = 0; c < n_cc; ++c) s += part[(int64_t)c * m + k];
-    out[k] = s * norm;
+    if (k < m)
+        for (int32_t c = q; c < n_cc; c += RLANES) s += part[(int64_t)c * m + k];
+    red[q][p] = s;
+    __syncthreads();
+    if (q == 0 && k < m) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < RLANES; ++l) t += red[l][p];
+        out[k] = t * norm;
+    }
 }
 
 hipError_t launch(const EvalArgs& a, hipStream_t s) {
@@ -206,7 +281,7 @@ hipError_t launch(const EvalArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(k_eval<1>, dim3((unsigned)items), dim3(BLOCK), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.n_cc == 1) return e;
-    const unsigned blocks = (unsigned)((a.m + BLOCK - 1) / BLOCK);
+    const unsigned blocks = (unsigned)((a.m + RPOINTS - 1) / RPOINTS);
     hipLaunchKernelGGL(k_eval_reduce, dim3(blocks), dim3(BLOCK), 0, s, a.part, a.n_cc, a.m, a.norm, a.out);
     return hipGetLastError();
 }

@@ -330,15 +330,42 @@ def kde_plugin_bandwidth_ex(ctx: int, x, check: bool = True) -> kde_result:
     return res
 
 
+def _device_batch(xs: Sequence):
+    """(pointers, sizes, stream) of a list of contiguous CUDA float64 tensors on
+    one device, or None if xs is anything else; one pass, no per-sample stream
+    lookups (the batch runs on the current stream of the samples' device)."""
+    if not xs or not all(_is_torch(x) for x in xs):
+        return None
+    t = _torch()
+    dev = xs[0].device
+    if dev.type != "cuda":
+        return None
+    for x in xs:
+        if x.device != dev or x.dtype != t.float64 or not x.is_contiguous():
+            return None
+    m = len(xs)
+    ptrs = (_P * m)(*[x.data_ptr() for x in xs])
+    ns = (_I64 * m)(*[x.numel() for x in xs])
+    return ptrs, ns, _current_stream(dev)
+
+
 def kde_plugin_bandwidth_batch(ctx: int, xs: Sequence) -> List[kde_result]:
     """All samples host (numpy) or all device (torch CUDA float64) arrays."""
+    xs = list(xs)
+    m = len(xs)
+    fast = _device_batch(xs)
+    if fast is not None:
+        ptrs, ns, stream = fast
+        out = (kde_result * m)()
+        _check(_lib.kde_plugin_bandwidth_batch(ctx, ptrs, ns, m, KDE_MEM_DEVICE, out, stream),
+               "kde_plugin_bandwidth_batch")
+        return list(out)
     ss = [_Samples(x if _is_torch(x) else _host_f64(x)) for x in xs]
     mems = {s.mem for s in ss}
     if len(mems) != 1:
         raise ValueError("batch samples must be all host or all device arrays")
     if any(s.dtype != KDE_F64 for s in ss):
         raise TypeError("batch samples must be float64")
-    m = len(ss)
     ptrs = (_P * m)(*[s.ptr for s in ss])
     ns = (_I64 * m)(*[s.n for s in ss])
     out = (kde_result * m)()

@@ -2,13 +2,18 @@
 GPU against the oracle's plain FP64 definition, through the C ABI.
 
 Tolerances.  FP64: both sides add n positive terms, so each is within
-(n - 1) u of the exact sum (u = 2^-53); the test allows 2 n u.  FP32: the
-relative error of a term 2^(-d^2) with d = v_y - v_x is about
-2 ln2 |d| |delta d|, where delta d is the FP32 rounding of the centred scaled
-values (at most 2^-24 (|v_y| + |v_x| + |d|), |v_y| <= 4 in a narrow tile);
-over the terms that matter (|d| <= 5) this stays below 1e-5, and the sums of
-positive terms add a few 2^-24.  Points where the density is below 1e-30 of
-its maximum (terms below FP32's range) are not compared.
+(n - 1) u of the exact sum (u = 2^-53); the test allows 2 n u.  FP32 (u32 =
+2^-24): a term 2^(-d^2), d = v_y - v_x, is computed from the FP32-rounded
+centred scaled values as 2^(-v_y^2) 2^(a), a = fma(v_x, 2 v_y, -fl(v_x^2)),
+on narrow groups of points (|v_y| <= 4).  Its relative error is
+ln2 |delta a| + 2 ln2 |d| |delta d| + (exp2's rounding, ~u32), with
+|delta a| <= u32 (v_x^2 + |a|) from the rounding of v_x^2 and of the fma, and
+|delta d| <= u32 (|v_y| + |v_x|) from the rounding of the centred values.
+Over the terms that matter (|d| <= 5, so |v_x| <= 9 and |a| <= 25) that is
+at most 4.4e-6 + 5.4e-6 + 1e-7, below 1e-5; wide groups take the
+differences in FP64 (only the square's and exp2's rounding, a few u32 times
+d^2).  The sums of positive terms add a few u32.  Points where the density is
+below 1e-30 of its maximum (terms below FP32's range) are not compared.
 """
 import math
 
