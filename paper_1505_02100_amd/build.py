@@ -68,6 +68,52 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SAN_DIR = os.path.join(ROOT, "tests", "sanitize")
+SAN_EXE = os.path.join(SAN_DIR, "kde_san_driver")
+# the translation units whose host code the sanitizer build instruments; the
+# device-heavy units are linked from the ordinary build unchanged
+SAN_HOST_SOURCES = ["kde_host.cpp", "kde_tune.cpp", "kde_server.cpp", "kde_noalloc.hip"]
+SAN_HOST_FLAGS = ["-g", "-O1", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=all"]
+CLANG = os.environ.get("KDE_CLANGXX", "/opt/rocm/llvm/bin/clang++")
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """tests/sanitize/kde_san_driver: the C ABI driver linked with the host
+    runtime built under AddressSanitizer and UndefinedBehaviorSanitizer (host
+    code only; kde_device.o and kde_eval.o come from build())."""
+    objdir = os.path.join(SAN_DIR, "obj")
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    base = [f for f in FLAGS if f not in ("-O3",)]
+    for src, path in [(s_, os.path.join(CSRC, s_)) for s_ in SAN_HOST_SOURCES] + \
+                     [("kde_san_driver.cpp", os.path.join(SAN_DIR, "kde_san_driver.cpp"))]:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC, *base, *SAN_HOST_FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", "-c", path, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src} (sanitizer build):\n{r.stdout}\n{r.stderr}")
+        objs.append(obj)
+    for src in ("kde_device.hip", "kde_eval.hip"):
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        if not os.path.exists(obj):
+            raise RuntimeError(f"{obj} missing: build() first")
+        objs.append(obj)
+    tmp = SAN_EXE + ".tmp"
+    cmd = [CLANG, "-fsanitize=undefined,address", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,/opt/rocm/lib", "-lstdc++", "-lm"]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"sanitizer driver link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SAN_EXE)
+    return SAN_EXE
+
+
 PROBE_SRC = os.path.join(HERE, "probes", "issue_rate.hip")
 PROBE = os.path.join(HERE, "probes", "issue_rate")
 
@@ -90,3 +136,4 @@ def build_probe(verbose: bool = False) -> str:
 if __name__ == "__main__":
     print(build(verbose=True))
     print(build_probe(verbose=True))
+    print(build_sanitized(verbose=True))

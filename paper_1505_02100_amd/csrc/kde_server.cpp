@@ -396,6 +396,7 @@ int launch_step(kde_server* s) {
     HIPCHK(hipEventSynchronize(s->items_free[b]));  // the previous copy out of this buffer is done
     Item* dst = s->h_items[b];
     for (auto& v : stage_lists) {
+        if (v.empty()) continue;
         std::memcpy(dst, v.data(), v.size() * sizeof(Item));
         dst += v.size();
     }
@@ -476,8 +477,8 @@ int retire_step(kde_server* s, bool block) {
             kde_completion c{};
             fill_result(h, &c.result);
             if (c.result.status) c.result.h = NAN;
-            complete(s, k, c, t);
             s->pairs_done += r.pairs;
+            complete(s, k, c, t);  // erases active[k]: r is gone after this
         } else {
             ++k;
         }
