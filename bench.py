@@ -278,9 +278,9 @@ def bench_serve(args):
     prec = {"fp32": kp.KDE_FP32_COMP, "fp32x": kp.KDE_FP32_COMP_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
             "q32": kp.KDE_Q32_32, "fp64": kp.KDE_FP64_PLAIN}
     trace = synth.serving_trace(rate=args.rate, duration=args.duration, master=4)
-    # items of about 2^24 pairs for every request size: a step of 2^36 pairs then
-    # holds thousands of items from many requests
-    ctx = kp.Context(prec[args.precision], pair_budget=1 << 24)
+    # items of about 2^pair_budget_log2 pairs for every request size: a step of
+    # 2^36 pairs then holds thousands of items from many requests
+    ctx = kp.Context(prec[args.precision], pair_budget=1 << args.pair_budget_log2)
     ctx.plugin_bandwidth(synth.normal(4096, 1))
     rep = serve_trace(ctx, trace, duration_s=args.duration, mem_budget=8 << 30, max_active=args.max_active,
                       step_pairs=1 << 36, policy=args.policy, aging_ms=args.aging_ms, fill=args.fill,
@@ -310,6 +310,7 @@ def bench_serve(args):
            "config": {"workload": f"serving: Poisson arrivals {args.rate}/s for {args.duration}s, n log-uniform "
                                   "in [1e3, 4e6], N(0,1)/bimodal/t3, samples resident on device, admission "
                                   "capped at 8 GiB", "policy": args.policy, "aging_ms": args.aging_ms, "fill": args.fill,
+                      "pair_budget_log2": args.pair_budget_log2,
                       "max_active": args.max_active, "precision": args.precision, "drain": args.drain},
            "value_is": "pair evaluations of completed requests per second of the run",
            "selections_per_s": round(rep["selections_per_s"], 3),
@@ -378,6 +379,8 @@ def main():
                     help="serve, sjf: a queued request's key drops by one (a halving of its pair count) per "
                          "this many ms of waiting; 0 = pure smallest first")
     ap.add_argument("--drain", action="store_true", help="serve: run until every arrival has finished")
+    ap.add_argument("--pair-budget-log2", type=int, default=22,
+                    help="serve: work items of about 2^this many pairs (the step holds 2^36)")
     ap.add_argument("--fill", choices=["share", "priority"], default="priority",
                     help="serve: a step's pair budget round-robin over the active requests, or in key order")
     ap.add_argument("--tune-table", default=None, help="autotune table for the batch workload")

@@ -368,9 +368,14 @@ KDE_API int kde_server_create(kde_server** out, kde_ctx* ctx, const kde_server_o
 KDE_API void kde_server_destroy(kde_server* srv);
 /* Queue one FP64 sample x[0..n) (host or device memory).  Host samples are
  * copied to the device at admission, so x must stay valid until the request
- * is admitted (device samples: until it completes).  *id identifies it.
- * KDE_ENOMEM if it could never fit the memory budget. */
-KDE_API int kde_server_submit(kde_server* srv, const void* x, int64_t n, int mem_kind, int64_t* id);
+ * is admitted (device samples: until it completes).  For a device sample,
+ * `producer` is the stream whose work writes x (NULL: the null stream): the
+ * server records an event there at submission and its own stream waits for
+ * it before the first step that reads x, so the sample may still be in
+ * flight when it is submitted (ignored for host samples).  *id identifies the
+ * request.  KDE_ENOMEM if it could never fit the memory budget. */
+KDE_API int kde_server_submit(kde_server* srv, const void* x, int64_t n, int mem_kind, kde_stream producer,
+                              int64_t* id);
 /* Remove a request that is still queued; KDE_EBUSY once admitted. */
 KDE_API int kde_server_cancel(kde_server* srv, int64_t id);
 /* Retire finished steps, admit queued requests, and launch the next step if

@@ -95,8 +95,8 @@ struct Request {
     int64_t next = 0;                 // and (row block, chunk) for pair stages
     int64_t rb = 0, cb = 0;
     double pairs = 0;                 // pair evaluations of the whole selection
-    hipEvent_t copied = nullptr;      // sample copy done (host samples)
-    bool wait_copy = false;
+    hipEvent_t copied = nullptr;      // sample ready: host copy done, or the producer's work (device samples)
+    bool wait_copy = false;           // the compute stream has yet to wait for `copied`
     int64_t last_step = -1;           // sequence number of the step that listed its last items
     int64_t launched_step = -1;       // sequence number of the last launched step listing any of its items
     double listed_pairs = 0;          // pair evaluations of the items listed so far
@@ -185,6 +185,7 @@ int admit_one(kde_server* s, std::unique_ptr<Request>& rp) {
         r.desc.x = dst;
     } else {
         r.desc.x = r.x_user;
+        r.wait_copy = r.copied != nullptr;  // the producer stream's event recorded at submission
     }
     r.geom = pair_geom(s->ctx, r.n);
     r.stage = 0;
@@ -564,6 +565,8 @@ void kde_server_destroy(kde_server* s) {
     for (auto& st : s->inflight) (void)hipEventDestroy(st.done);
     for (auto& r : s->active)
         if (r->copied) (void)hipEventDestroy(r->copied);
+    for (auto& r : s->queue)
+        if (r->copied) (void)hipEventDestroy(r->copied);
     for (int q = 0; q < 2; ++q) {
         if (s->h_items[q]) (void)hipHostFree(s->h_items[q]);
         if (s->items_free[q]) (void)hipEventDestroy(s->items_free[q]);
@@ -576,21 +579,33 @@ void kde_server_destroy(kde_server* s) {
     delete s;
 }
 
-int kde_server_submit(kde_server* s, const void* x, int64_t n, int mem_kind, int64_t* id) {
+int kde_server_submit(kde_server* s, const void* x, int64_t n, int mem_kind, kde_stream producer, int64_t* id) {
     if (!s || !id) return set_err(KDE_EINVAL, "null server or id");
     int st = check_x(x, n, 2, mem_kind, KDE_F64);
     if (st) return st;
     auto r = std::make_unique<Request>();
-    r->id = s->next_id++;
     r->x_user = x;
     r->n = n;
     r->mem_kind = mem_kind;
-    r->t_submit = now_ms();
     SampleSpec sp{x, n, KDE_F64, MODE_PLUGIN, 0, 0.0, 0, -1};
     describe_sample(s->ctx, sp, &r->desc);
     r->bytes = request_bytes(*r);
     if (budget_bytes(*r) > (size_t)s->opt.mem_budget)
         return set_err(KDE_ENOMEM, "request larger than the server's memory budget");
+    if (mem_kind == KDE_MEM_DEVICE) {
+        // the sample may still be being written on the producer's stream: the
+        // server's stream waits for the work enqueued there so far before the
+        // first step that lists the request
+        DeviceGuard dg(s->ctx->device);
+        HIPCHK(hipEventCreateWithFlags(&r->copied, hipEventDisableTiming));
+        const hipError_t e = hipEventRecord(r->copied, (hipStream_t)producer);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(r->copied);
+            return hip_fail(e, "hipEventRecord on the producer stream");
+        }
+    }
+    r->id = s->next_id++;
+    r->t_submit = now_ms();
     r->pairs = (double)n * (double)(n - 1);
     *id = r->id;
     s->queue.push_back(std::move(r));
@@ -601,6 +616,7 @@ int kde_server_cancel(kde_server* s, int64_t id) {
     if (!s) return set_err(KDE_EINVAL, "null server");
     for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
         if ((*it)->id == id) {
+            if ((*it)->copied) (void)hipEventDestroy((*it)->copied);
             s->queue.erase(it);
             return ok();
         }

@@ -156,7 +156,7 @@ _sig("kde_psi_num_items", _I64, _P, _I64)
 _sig("kde_server_options_init", None, ctypes.POINTER(kde_server_options))
 _sig("kde_server_create", ctypes.c_int, ctypes.POINTER(_P), _P, ctypes.POINTER(kde_server_options))
 _sig("kde_server_destroy", None, _P)
-_sig("kde_server_submit", ctypes.c_int, _P, _P, _I64, ctypes.c_int, _PI64)
+_sig("kde_server_submit", ctypes.c_int, _P, _P, _I64, ctypes.c_int, _P, _PI64)
 _sig("kde_server_cancel", ctypes.c_int, _P, _I64)
 _sig("kde_server_step", ctypes.c_int, _P, _I32, ctypes.POINTER(kde_server_stats))
 _sig("kde_server_poll", ctypes.c_int, _P, ctypes.POINTER(kde_completion), _I32, _PI32)
@@ -495,9 +495,12 @@ def kde_server_destroy(srv: int) -> None:
     _lib.kde_server_destroy(srv)
 
 
-def kde_server_submit(srv: int, ptr: int, n: int, mem_kind: int) -> int:
+def kde_server_submit(srv: int, ptr: int, n: int, mem_kind: int, producer=None) -> int:
+    """producer: the raw HIP stream that writes a device sample (None: the null
+    stream); the server's work on the sample is ordered after it."""
     rid = _I64()
-    _check(_lib.kde_server_submit(srv, ptr, int(n), int(mem_kind), ctypes.byref(rid)), "kde_server_submit")
+    _check(_lib.kde_server_submit(srv, ptr, int(n), int(mem_kind), producer, ctypes.byref(rid)),
+           "kde_server_submit")
     return rid.value
 
 

@@ -79,7 +79,8 @@ class Server:
         s = kp._Samples(x)
         if s.dtype != kp.KDE_F64:
             raise TypeError("server samples must be float64")
-        rid = kp.kde_server_submit(self.handle, s.ptr, s.n, s.mem)
+        # a device tensor's producer is torch's current stream on its device
+        rid = kp.kde_server_submit(self.handle, s.ptr, s.n, s.mem, s.stream)
         self._keep[rid] = s.keep
         return rid
 

@@ -256,14 +256,14 @@ static void server_calls() {
         std::vector<int64_t> ids;
         for (auto& v : xs) {
             int64_t id = 0;
-            CHECK(kde_server_submit(s, v.data(), (int64_t)v.size(), KDE_MEM_HOST, &id) == KDE_OK);
+            CHECK(kde_server_submit(s, v.data(), (int64_t)v.size(), KDE_MEM_HOST, nullptr, &id) == KDE_OK);
             ids.push_back(id);
         }
         int64_t idd = 0;
-        CHECK(kde_server_submit(s, d, (int64_t)xs[9].size(), KDE_MEM_DEVICE, &idd) == KDE_OK);
+        CHECK(kde_server_submit(s, d, (int64_t)xs[9].size(), KDE_MEM_DEVICE, nullptr, &idd) == KDE_OK);
         std::vector<double> huge_host(1);
         int64_t idh = 0;
-        CHECK(kde_server_submit(s, huge_host.data(), (int64_t)1 << 30, KDE_MEM_HOST, &idh) == KDE_ENOMEM);
+        CHECK(kde_server_submit(s, huge_host.data(), (int64_t)1 << 30, KDE_MEM_HOST, nullptr, &idh) == KDE_ENOMEM);
         CHECK(kde_server_cancel(s, ids.back()) == KDE_OK);
         kde_server_stats st{};
         CHECK(kde_server_step(s, 0, &st) == KDE_OK);

@@ -183,3 +183,24 @@ def test_priority_fill_finishes_in_key_order(kp, ctx):
     assert done["priority"][0] < done["priority"][-1]
     span = lambda t: max(t) - min(t)
     assert span(done["share"]) < span(done["priority"])
+
+
+def test_device_sample_written_on_another_stream(kp, ctx):
+    # the sample is still being written on a side stream (behind a ~20 ms spin)
+    # when it is submitted; the server's stream waits for that stream's work
+    import torch
+    from paper_1505_02100_amd.server import Server
+    x = synth.draw("t3", 30000, 77)
+    src = torch.from_numpy(x).cuda()
+    dst = torch.full_like(src, float("nan"))
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with Server(ctx, max_active=4, step_pairs=1 << 26) as srv:
+        with torch.cuda.stream(side):
+            torch.cuda._sleep(50_000_000)
+            dst.copy_(src)
+            rid = srv.submit(dst)            # producer: the side stream
+        res = {c.id: c for c in srv.drain()}
+    torch.cuda.synchronize()
+    alone = ctx.plugin_bandwidth(src)
+    assert res[rid].status == 0 and (res[rid].h, res[rid].psi6, res[rid].psi4) == (alone.h, alone.psi6, alone.psi4)
