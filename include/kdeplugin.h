@@ -411,10 +411,16 @@ KDE_API int kde_server_fail_next_step(kde_server* srv, int32_t code);
  *     count per size (table key "targets");
  *   mode KDE_TUNE_BATCH: all samples in one kde_plugin_bandwidth_batch
  *     launch; items are sized to a pair budget B (table key "pair_budget").
+ * For KDE_FP32_COMP the search also times the other way to evaluate 2^t in
+ * the pair terms, the Remez minimax polynomial on the FMA pipes (the kernels
+ * of KDE_FP32_POLYEXP), and records the faster as "exp_poly" (0: v_exp_f32,
+ * 1: the polynomial); a context created with such a table uses it.
  * The table is written to out_path as JSON and read back through
- * kde_options.tune_table.  None of these parameters changes what is
- * computed; for a given table results are deterministic.  verbose != 0
- * prints every timing to stderr.  Synchronous. */
+ * kde_options.tune_table.  R, the blocks per CU and the item sizes do not
+ * change what is computed; the exponential's choice changes results at the
+ * rounding level only (both within the FP32 bounds).  For a given table
+ * results are deterministic.  verbose != 0 prints every timing to stderr.
+ * Synchronous. */
 #define KDE_TUNE_SINGLE 0
 #define KDE_TUNE_BATCH 1
 KDE_API int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t count, int32_t mode,

@@ -117,6 +117,7 @@ int64_t target_items_for(const kde_ctx* c, int64_t n) {
 // pairs.
 struct TuneTable {
     int precision = -1, R = 0, bpc = 0;
+    int exp_poly = -1;  // FP32: 1 = the polynomial exponential won the search
     int64_t bucket[64] = {0};
     int64_t pair_budget = 0;
 };
@@ -144,6 +145,7 @@ int load_tune_table(const char* path, TuneTable* tt) {
     if (json_int(t, "rows_per_lane", &v)) tt->R = (int)v;
     if (json_int(t, "blocks_per_cu", &v)) tt->bpc = (int)v;
     if (json_int(t, "pair_budget", &v)) tt->pair_budget = v;
+    if (json_int(t, "exp_poly", &v)) tt->exp_poly = (int)v;
     const size_t k = t.find("\"targets\"");
     if (k != std::string::npos) {
         const size_t open = t.find('[', k);
@@ -163,7 +165,8 @@ int load_tune_table(const char* path, TuneTable* tt) {
             ++pos;
         }
     }
-    if ((tt->R != 0 && tt->R != 1 && tt->R != 2 && tt->R != 4) || tt->bpc < 0 || tt->bpc > 16)
+    if ((tt->R != 0 && tt->R != 1 && tt->R != 2 && tt->R != 4) || tt->bpc < 0 || tt->bpc > 16 ||
+        tt->exp_poly < -1 || tt->exp_poly > 1 || (tt->exp_poly == 1 && tt->precision != KDE_FP32_COMP))
         return set_err(KDE_EINVAL, std::string("malformed tune table ") + path);
     return KDE_OK;
 }
@@ -657,7 +660,8 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     for (int b = 0; b < 64; ++b) c->bucket_target[b] = tt.bucket[b];
     c->pair_budget = o.pair_budget > 0 ? o.pair_budget : tt.pair_budget;
     c->device = o.device;
-    c->precision = o.precision;
+    // an FP32 tune table may select the polynomial exponential's kernels
+    c->precision = (o.precision == KDE_FP32_COMP && tt.exp_poly == 1) ? KDE_FP32_POLYEXP : o.precision;
     c->mem_budget = o.mem_budget;
     c->R = o.rows_per_lane ? o.rows_per_lane : (tt.R ? tt.R : 1);
     c->target_items = o.target_items;

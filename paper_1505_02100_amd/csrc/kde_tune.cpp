@@ -5,9 +5,13 @@
 // per CU, and the number of pair items a stage is cut into (which sets the
 // item width W for each sample size).  R and the block count are fixed per
 // context (they pick the kernel instantiation and grid); the item count is
-// chosen per sample size.  The search times complete selections of
-// synthetic samples with HIP events around each launch and writes the best
-// configuration as a table that kde_ctx_create reads back.
+// chosen per sample size.  For the FP32 precision there is a fourth: how
+// 2^t is evaluated, on the transcendental unit (v_exp_f32) or by the Remez
+// minimax polynomial on the FMA pipes (the paper's exponential); the two
+// agree to rounding level, well inside the FP32 bound.  The search times
+// complete selections of synthetic samples with HIP events around each
+// launch and writes the best configuration as a table that kde_ctx_create
+// reads back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -84,11 +88,12 @@ double time_batch(kde_ctx* c, const std::vector<void*>& dx, const std::vector<in
 }
 
 int write_table(const char* out_path, int precision, int R, int bpc, double total,
-                const std::vector<std::pair<int, int64_t>>& ent, int64_t budget) {
+                const std::vector<std::pair<int, int64_t>>& ent, int64_t budget, int exp_poly = -1) {
     FILE* f = std::fopen(out_path, "w");
     if (!f) return KDE_EINVAL;
     std::fprintf(f, "{\n \"precision\": %d,\n \"rows_per_lane\": %d,\n \"blocks_per_cu\": %d,\n", precision, R,
                  bpc);
+    if (exp_poly >= 0) std::fprintf(f, " \"exp_poly\": %d,\n", exp_poly);
     std::fprintf(f, " \"total_ms\": %.6f,\n", total);
     if (budget > 0) {
         std::fprintf(f, " \"pair_budget\": %lld\n}\n", (long long)budget);
@@ -126,15 +131,21 @@ extern "C" int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t c
             st = KDE_EDEVICE;
     }
     const int Rs[] = {1, 2, 4};
+    // the FP32 precision also tries the polynomial exponential (its kernels are
+    // those of KDE_FP32_POLYEXP); other precisions have one way to evaluate it
+    const bool try_poly = base.precision == KDE_FP32_COMP;
+    const int exp_choices = try_poly ? 2 : 1;
     if (st == KDE_OK && mode == 1) {
         // batch objective: one launch over all samples; item size = pair budget
         const int64_t budgets[] = {1 << 18, 1 << 19, 1 << 20, 1 << 21, 1 << 22, 1 << 23};
         double bt = 1e300;
-        int bR = 1, bB = 0;
+        int bR = 1, bB = 0, bP = 0;
         int64_t bbud = 0;
+        for (int ep = 0; ep < exp_choices; ++ep)
         for (int R : Rs) {
             kde_options o = base;
             o.rows_per_lane = R;
+            if (ep) o.precision = KDE_FP32_POLYEXP;
             kde_ctx* probe = nullptr;
             if (kde_ctx_create(&probe, &o) != KDE_OK) {
                 st = KDE_EDEVICE;
@@ -150,7 +161,7 @@ extern "C" int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t c
                     std::snprintf(path, sizeof path, "/tmp/kde_tune_probe_%d.json", (int)getpid());
                     o.blocks_per_cu = bpc;
                     std::vector<std::pair<int, int64_t>> none;
-                    if (write_table(path, base.precision, R, bpc, 0.0, none, B) != KDE_OK) continue;
+                    if (write_table(path, o.precision, R, bpc, 0.0, none, B) != KDE_OK) continue;
                     kde_options ot = o;
                     ot.tune_table = path;
                     kde_ctx* c = nullptr;
@@ -159,13 +170,14 @@ extern "C" int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t c
                     kde_ctx_destroy(c);
                     std::remove(path);
                     if (verbose)
-                        std::fprintf(stderr, "autotune batch R=%d bpc=%d budget=%lld: %.4f ms\n", R, bpc,
-                                     (long long)B, ms);
+                        std::fprintf(stderr, "autotune batch exp=%s R=%d bpc=%d budget=%lld: %.4f ms\n",
+                                     ep ? "poly" : "hw", R, bpc, (long long)B, ms);
                     if (ms > 0 && ms < bt) {
                         bt = ms;
                         bR = R;
                         bB = bpc;
                         bbud = B;
+                        bP = ep;
                     }
                 }
             }
@@ -174,19 +186,21 @@ extern "C" int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t c
             if (p) (void)hipFree(p);
         if (st) return st;
         std::vector<std::pair<int, int64_t>> none;
-        return write_table(out_path, base.precision, bR, bB, bt, none, bbud);
+        return write_table(out_path, base.precision, bR, bB, bt, none, bbud, try_poly ? bP : -1);
     }
     const int64_t targets[] = {1024, 2048, 4096, 8192, 16384, 32768, 65536};
     struct Best {
         double total = 1e300;
-        int R = 1, bpc = 0;
+        int R = 1, bpc = 0, poly = 0;
         std::vector<int64_t> tgt;
     } best;
+    for (int ep = 0; ep < exp_choices; ++ep)
     for (int R : Rs) {
         if (st) break;
         // blocks per CU: the occupancy limit and one below it
         kde_options o = base;
         o.rows_per_lane = R;
+        if (ep) o.precision = KDE_FP32_POLYEXP;
         kde_ctx* probe = nullptr;
         if (kde_ctx_create(&probe, &o) != KDE_OK) {
             st = KDE_EDEVICE;
@@ -208,8 +222,8 @@ extern "C" int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t c
                     const double ms = time_ctx(c, dx[q], sizes[q], reps);
                     kde_ctx_destroy(c);
                     if (verbose)
-                        std::fprintf(stderr, "autotune R=%d bpc=%d n=%lld items=%lld: %.4f ms\n", R, bpc,
-                                     (long long)sizes[q], (long long)T, ms);
+                        std::fprintf(stderr, "autotune exp=%s R=%d bpc=%d n=%lld items=%lld: %.4f ms\n",
+                                     ep ? "poly" : "hw", R, bpc, (long long)sizes[q], (long long)T, ms);
                     if (ms > 0 && ms < bt) {
                         bt = ms;
                         tgt[q] = T;
@@ -222,6 +236,7 @@ extern "C" int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t c
                 best.R = R;
                 best.bpc = bpc;
                 best.tgt = tgt;
+                best.poly = ep;
             }
         }
     }
@@ -232,5 +247,5 @@ extern "C" int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t c
     std::vector<std::pair<int, int64_t>> ent;
     for (size_t q = 0; q < sizes.size(); ++q) ent.emplace_back(floor_log2(sizes[q]), best.tgt[q]);
     std::sort(ent.begin(), ent.end());
-    return write_table(out_path, base.precision, best.R, best.bpc, best.total, ent, 0);
+    return write_table(out_path, base.precision, best.R, best.bpc, best.total, ent, 0, try_poly ? best.poly : -1);
 }

@@ -381,3 +381,30 @@ def test_autotune_tables_roundtrip(kp, tmp_path):
         _check(res[0], ref, TOL32_H, TOL32_PSI)
     with pytest.raises(kp.KdeError):
         kp.Context(kp.KDE_FP64_PLAIN, tune_table=p1)
+    # the FP32 search also times the polynomial exponential and records its pick
+    assert t1["exp_poly"] in (0, 1) and t2["exp_poly"] in (0, 1)
+
+
+def test_tune_table_selects_the_polynomial_exponential(kp, tmp_path):
+    # an FP32 table with exp_poly = 1 runs the polynomial-exponential kernels:
+    # bitwise what a KDE_FP32_POLYEXP context computes, within the FP32 bounds
+    # of the oracle; exp_poly = 0 keeps v_exp_f32; a table for another
+    # precision may not select it
+    x = synth.student_t3(5000, 31)
+    ref = oracle.plugin(x)
+    with kp.Context(kp.KDE_FP32_POLYEXP) as cp, kp.Context(kp.KDE_FP32_COMP) as ch:
+        rp, rh = cp.plugin_bandwidth(x), ch.plugin_bandwidth(x)
+    for flag, want in ((1, rp), (0, rh)):
+        p = str(tmp_path / f"exp{flag}.json")
+        with open(p, "w") as f:
+            f.write('{"precision": %d, "rows_per_lane": 1, "blocks_per_cu": 0, "exp_poly": %d}' %
+                    (kp.KDE_FP32_COMP, flag))
+        with kp.Context(kp.KDE_FP32_COMP, tune_table=p) as c:
+            r = c.plugin_bandwidth(x)
+        assert (r.h, r.psi6, r.psi4) == (want.h, want.psi6, want.psi4), flag
+        _check(r, ref, TOL32_H, TOL32_PSI)
+    bad = str(tmp_path / "bad.json")
+    with open(bad, "w") as f:
+        f.write('{"precision": %d, "exp_poly": 1}' % kp.KDE_FP64_PLAIN)
+    with pytest.raises(kp.KdeError):
+        kp.Context(kp.KDE_FP64_PLAIN, tune_table=bad)
