@@ -272,7 +272,10 @@ KDE_API int kde_psi_item_geometry(const kde_ctx* ctx, int64_t n, int64_t item, i
 
 /* Partial sum of one Psi stage over the contiguous pair items
  * [item_begin, item_end):  *partial = sum over those items' pairs i < j of
- * K^(r)((x_i - x_j)/g), in the context's precision with an FP64 total.
+ * K^(r)((x_i - x_j)/g), in the context's precision; each item's FP64 partial
+ * is added exactly in 128-bit fixed point with a resolution of 2^-64 (so the
+ * total does not depend on the order of the items, and a partial is exact to
+ * within 2^-64 per item on top of the items' own rounding).
  * This is one shard of Step IV/VI: the shards of a partition of
  * [0, kde_psi_num_items) add up to the full strict-upper-triangle sum.
  * Synchronous. */

@@ -207,3 +207,37 @@ def test_batch_512(kp, ctxs, batch512):
     for k in (0, 1, 77, 311, 511):
         s = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth(xds[k])
         assert (s.h, s.psi6, s.psi4) == (b32[k].h, b32[k].psi6, b32[k].psi4)
+
+
+def test_quarter_billion_samples_tail_items(kp, ctxs):
+    # n = 2^28 + 3 (2 GB on the device): work items at the end of the pair
+    # enumeration, where row and column offsets are ~2.7e8 and the pair
+    # counts of the stage exceed 2^55, against the oracle's block sums over
+    # the same rectangles (only those slices go to the host); Step I runs
+    # over the whole sample for the centring.  The bandwidths are the ones the
+    # selector takes at this size for N(0, 1): g1 = (6.465/n)^(1/9) = 0.14 for
+    # Step IV, about half of it for Step VI (the FP32 path's accuracy needs
+    # max |x - centre| / g within a few hundred, as the selector's g gives)
+    import torch
+    n = (1 << 28) + 3
+    xd = synth.draw_torch("normal", n, 51)
+    torch.cuda.synchronize()
+    gs = {6: (6.465 / n) ** (1 / 9), 4: 0.5 * (6.465 / n) ** (1 / 9)}
+    for p, eps in ((kp.KDE_FP64_PLAIN, 1e-13), (kp.KDE_FP32_COMP, 2e-6)):
+        ctx = ctxs[p]
+        m = ctx.psi_num_items(n)
+        assert m > 1 << 16
+        for k in (m - 1, m - 2, m - 9, m - 500):
+            r0, r1, c0, c1 = ctx.psi_item_geometry(n, k)
+            assert 0 <= r0 < r1 <= n and r0 <= c0 < c1 <= n
+            xs = xd[r0:c1].cpu().numpy()       # rows and columns of the item, re-based at r0
+            for r in (4, 6):
+                g = gs[r]
+                got = ctx.psi_range(xd, r, g, k, k + 1)
+                ref = oracle.block_sum(xs, r, g, 0, r1 - r0, c0 - r0, c1 - r0)
+                # item partials are added exactly in fixed point with a
+                # resolution of 2^-64 (an absolute term for the tiny last items)
+                bound = eps * _abs_block_sum(xs, r, g, 0, r1 - r0, c0 - r0, c1 - r0) + 2.0 ** -64
+                assert abs(got - ref) <= bound, (p, k, r, got, ref, bound)
+    del xd
+    torch.cuda.empty_cache()
