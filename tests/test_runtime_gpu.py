@@ -1,0 +1,127 @@
+"""The host runtime around the kernels, through the C ABI: the context's
+device-memory budget and its plan cache (eviction and reuse), contexts used
+from several host threads at once (one context per thread, and the literal
+calls' shared default context), and thread-local error state.  Results must
+be bitwise those of the same calls made one at a time."""
+import ctypes
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_02100_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kp():
+    from paper_1505_02100_amd import kdeplugin
+    return kdeplugin
+
+
+def test_memory_budget_refuses_and_evicts(kp):
+    import torch
+    # device samples: the budget then covers the plans alone (work lists,
+    # slots, states: about 10, 61 and 181 KB for these sizes)
+    xs = [torch.from_numpy(synth.normal(n, 60 + n)).cuda() for n in (3000, 20000, 70000)]
+    with kp.Context(kp.KDE_FP32_COMP) as free:
+        want = [free.plugin_bandwidth(x) for x in xs]
+    # a budget below one plan refuses the call
+    with kp.Context(kp.KDE_FP32_COMP, mem_budget=4096) as tiny:
+        with pytest.raises(kp.KdeError) as e:
+            tiny.plugin_bandwidth(xs[2])
+        assert e.value.code == kp.KDE_ENOMEM
+    # a budget that holds the largest plan but not two of the larger ones:
+    # a new size evicts the least recently used plans, and revisiting a size
+    # rebuilds its plan with equal results
+    with kp.Context(kp.KDE_FP32_COMP, mem_budget=200 << 10) as small:
+        for _ in range(2):
+            for x, w in zip(xs, want):
+                r = small.plugin_bandwidth(x)
+                assert (r.h, r.psi6, r.psi4) == (w.h, w.psi6, w.psi4)
+
+
+def test_plan_cache_beyond_its_capacity(kp):
+    # more distinct sizes than the cache keeps (16): results stay bitwise equal
+    sizes = [300 + 97 * k for k in range(24)]
+    xs = [synth.bimodal(n, n) for n in sizes]
+    with kp.Context(kp.KDE_FP64_PLAIN) as c:
+        first = [c.plugin_bandwidth(x).h for x in xs]
+        again = [c.plugin_bandwidth(x).h for x in reversed(xs)][::-1]
+    assert first == again
+    for k in (0, 23):
+        assert abs(first[k] - oracle.plugin(xs[k]).h) <= 1e-12 * first[k]
+
+
+def test_contexts_on_several_threads(kp):
+    # one context per thread, all launching at once (ctypes releases the GIL)
+    xs = [synth.draw(synth.DISTS[k % 3], 5000 + 1111 * k, 70 + k) for k in range(6)]
+    with kp.Context(kp.KDE_FP32_COMP) as c:
+        want = [c.plugin_bandwidth(x).h for x in xs]
+    got = {}
+    errors = []
+
+    def work(t):
+        try:
+            with kp.Context(kp.KDE_FP32_COMP) as ctx:
+                got[t] = [[ctx.plugin_bandwidth(x).h for x in xs] for _ in range(3)]
+        except Exception as exc:  # reported below
+            errors.append(exc)
+
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(120)
+    assert not errors, errors
+    for t in range(4):
+        for rep in got[t]:
+            assert rep == want
+
+
+def test_literal_calls_share_the_default_context_safely(kp):
+    xs = [synth.normal(2000 + 500 * k, 80 + k) for k in range(4)]
+    want = [kp.kde_plugin_bandwidth(x) for x in xs]
+    got = {}
+
+    def work(t):
+        got[t] = [kp.kde_plugin_bandwidth(xs[(t + k) % 4]) for k in range(8)]
+
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(120)
+    for t in range(4):
+        assert got[t] == [want[(t + k) % 4] for k in range(8)]
+
+
+def test_errors_are_per_thread(kp):
+    seen = {}
+    barrier = threading.Barrier(2)
+
+    def bad():
+        kp._lib.kde_psi_num_items(None, 10)       # sets KDE_EINVAL on this thread
+        barrier.wait()
+        barrier.wait()
+        seen["bad"] = kp.kde_last_error()
+
+    def good():
+        barrier.wait()
+        res = kp.kde_result()
+        x = np.ascontiguousarray(synth.normal(100, 1))
+        with kp.Context(kp.KDE_FP64_PLAIN) as c:
+            code = kp._lib.kde_plugin_bandwidth_ex(c.handle, x.ctypes.data, 100, kp.KDE_MEM_HOST, kp.KDE_F64,
+                                                   None, ctypes.byref(res))
+        seen["good"] = (code, kp.kde_last_error())
+        barrier.wait()
+
+    ta, tb = threading.Thread(target=bad), threading.Thread(target=good)
+    ta.start()
+    tb.start()
+    ta.join(60)
+    tb.join(60)
+    assert seen["bad"] == kp.KDE_EINVAL
+    assert seen["good"] == (kp.KDE_OK, kp.KDE_OK)
