@@ -75,6 +75,23 @@ def stored_oracle_record(workload, x):
     return {k: float.fromhex(v) for k, v in rec["plugin"].items()}
 
 
+def run_env():
+    """The versions and devices a line was measured with."""
+    import platform
+    import torch
+    prop = torch.cuda.get_device_properties(0)
+    from paper_1505_02100_amd import kdeplugin as kp
+    return {"device": prop.name, "gcn_arch": getattr(prop, "gcnArchName", None),
+            "compute_units": prop.multi_processor_count, "library": kp.kde_version(),
+            "torch": torch.__version__, "hip": torch.version.hip, "python": platform.python_version(),
+            "host_cpus": os.cpu_count()}
+
+
+def synth_sha256(x):
+    from paper_1505_02100_amd import synth
+    return synth.sha256(x)
+
+
 def make_sample(w):
     from paper_1505_02100_amd import synth
     if w["kind"] == "normal":
@@ -467,7 +484,8 @@ def main():
                                        for q, p in (("p10", 10), ("p50", 50), ("p90", 90))},
            "stage_timeline_ms": [round(t, 4) for t in timeline],
            "exp2_per_s_device": pairs / (dev_ms_avg * 1e-3),
-           "roofline": roofline}
+           "roofline": roofline,
+           "env": run_env(), "dataset_sha256": synth_sha256(x)}
 
     if not args.no_fp64_compare and args.precision != "fp64":
         ctx64 = kp.Context(kp.KDE_FP64_PLAIN)

@@ -1912,6 +1912,27 @@ hipError_t launch_persistent(int prec, int R, int grid, hipStream_t s, const Lau
     }
 }
 
+const void* persistent_kernel(int prec, int R) {
+    switch (prec * 8 + R) {
+    case 0 * 8 + 1: return (const void*)k_persistent<0, 1, 256>;
+    case 0 * 8 + 2: return (const void*)k_persistent<0, 2, 256>;
+    case 0 * 8 + 4: return (const void*)k_persistent<0, 4, 256>;
+    case 1 * 8 + 1: return (const void*)k_persistent<1, 1, 256>;
+    case 1 * 8 + 2: return (const void*)k_persistent<1, 2, 256>;
+    case 1 * 8 + 4: return (const void*)k_persistent<1, 4, 256>;
+    case 2 * 8 + 1: return (const void*)k_persistent<2, 1, 256>;
+    case 2 * 8 + 2: return (const void*)k_persistent<2, 2, 256>;
+    case 2 * 8 + 4: return (const void*)k_persistent<2, 4, 256>;
+    case 3 * 8 + 1: return (const void*)k_persistent<3, 1, 256>;
+    case 3 * 8 + 2: return (const void*)k_persistent<3, 2, 256>;
+    case 3 * 8 + 4: return (const void*)k_persistent<3, 4, 256>;
+    case 4 * 8 + 1: return (const void*)k_persistent<4, 1, 256>;
+    case 4 * 8 + 2: return (const void*)k_persistent<4, 2, 256>;
+    case 4 * 8 + 4: return (const void*)k_persistent<4, 4, 256>;
+    default: return nullptr;
+    }
+}
+
 hipError_t persistent_occupancy(int prec, int R, int* blocks_per_cu) {
     switch (prec * 8 + R) {
     case 0 * 8 + 1: return occ_one<0, 1>(blocks_per_cu);

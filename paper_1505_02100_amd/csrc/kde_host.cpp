@@ -332,8 +332,9 @@ int total_plan_bytes(const kde_ctx* c, size_t extra, size_t* out) {
     return KDE_OK;
 }
 
-// Allocate and upload a freshly built plan.
-int upload_plan(kde_ctx* c, Plan& p) {
+// Allocate and upload a freshly built plan; the work list goes up on the
+// call's stream, ahead of the plan's first launch there.
+int upload_plan(kde_ctx* c, Plan& p, hipStream_t s) {
     const size_t need = sizeof(Item) * std::max<size_t>(1, p.items.size()) +
                         sizeof(Desc) * std::max(1, p.count) + sizeof(State) * std::max(1, p.count) +
                         sizeof(Pub) * kPubReplicas * std::max(1, p.count) +
@@ -359,10 +360,12 @@ int upload_plan(kde_ctx* c, Plan& p) {
     HIPCHK(hipHostMalloc((void**)&p.h_descs, sizeof(Desc) * std::max(1, p.count), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&p.ev_upload, hipEventDisableTiming));
     if (!p.items.empty())
-        HIPCHK(hipMemcpy(p.d_items.p, p.items.data(), sizeof(Item) * p.items.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpyAsync(p.d_items.p, p.items.data(), sizeof(Item) * p.items.size(), hipMemcpyHostToDevice,
+                              s));
     if (!p.outmap.empty()) {
         if ((st = p.d_outmap.ensure(sizeof(int32_t) * p.outmap.size(), "batch output map"))) return st;
-        HIPCHK(hipMemcpy(p.d_outmap.p, p.outmap.data(), sizeof(int32_t) * p.outmap.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpyAsync(p.d_outmap.p, p.outmap.data(), sizeof(int32_t) * p.outmap.size(),
+                              hipMemcpyHostToDevice, s));
     }
     int64_t per_stage[NUM_STAGES] = {0};
     for (const Item& it : p.items) ++per_stage[it.stage];
@@ -402,24 +405,31 @@ LaunchArgs args_for(const kde_ctx* c, Plan& p) {
 // stream (k_results) before the reset.
 int run_plan(kde_ctx* c, Plan& p, hipStream_t s, kde_result* out = nullptr, bool timed = true) {
     if (!p.exec) {
-        hipStream_t cap;
-        HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        // the graph is built node by node, not captured from a stream: a
+        // capture would collide with legacy-stream calls that other threads'
+        // contexts make meanwhile
         hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            const LaunchArgs a = args_for(c, p);
-            hipError_t e1 = launch_persistent(c->precision, c->R, p.grid, cap, a);
-            hipError_t e2 = hipMemcpyAsync(p.h_states, p.d_states.p, sizeof(State) * p.count,
-                                           hipMemcpyDeviceToHost, cap);
-            e = hipStreamEndCapture(cap, &graph);
-            if (e == hipSuccess && (e1 != hipSuccess || e2 != hipSuccess)) e = e1 != hipSuccess ? e1 : e2;
-        }
+        HIPCHK(hipGraphCreate(&graph, 0));
+        LaunchArgs a = args_for(c, p);
+        void* kargs[] = {&a};
+        hipKernelNodeParams kn{};
+        kn.func = const_cast<void*>(persistent_kernel(c->precision, c->R));
+        kn.gridDim = dim3((unsigned)p.grid);
+        kn.blockDim = dim3(kBlock);
+        kn.sharedMemBytes = 0;
+        kn.kernelParams = kargs;
+        kn.extra = nullptr;
+        hipGraphNode_t knode = nullptr, mnode = nullptr;
+        hipError_t e = kn.func ? hipGraphAddKernelNode(&knode, graph, nullptr, 0, &kn) : hipErrorInvalidValue;
+        if (e == hipSuccess)
+            e = hipGraphAddMemcpyNode1D(&mnode, graph, &knode, 1, p.h_states, p.d_states.p, sizeof(State) * p.count,
+                                        hipMemcpyDeviceToHost);
         if (e == hipSuccess) e = hipGraphInstantiate(&p.exec, graph, nullptr, nullptr, 0);
-        if (graph) (void)hipGraphDestroy(graph);
-        (void)hipStreamDestroy(cap);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) {
+            (void)hipGetLastError();
             p.exec = nullptr;
-            return hip_fail(e, "graph capture of the persistent kernel");
+            return hip_fail(e, "graph of the persistent kernel");
         }
     }
     if (!p.ev_reset) HIPCHK(hipEventCreateWithFlags(&p.ev_reset, hipEventDisableTiming));
@@ -461,7 +471,7 @@ Plan* find_plan(kde_ctx* c, const std::string& key) {
     return nullptr;
 }
 
-int get_plan(kde_ctx* c, const std::string& key, const std::vector<SampleSpec>& ss, Plan** out,
+int get_plan(kde_ctx* c, const std::string& key, const std::vector<SampleSpec>& ss, hipStream_t s, Plan** out,
              const std::vector<int32_t>* outmap = nullptr) {
     Plan* p = find_plan(c, key);
     if (!p) {
@@ -469,7 +479,7 @@ int get_plan(kde_ctx* c, const std::string& key, const std::vector<SampleSpec>& 
         np->key = key;
         build_items(c, *np, ss);
         if (outmap) np->outmap = *outmap;
-        int st = upload_plan(c, *np);
+        int st = upload_plan(c, *np, s);
         if (st) return st;
         c->plans.push_front(std::move(np));
         while (c->plans.size() > c->max_plans) c->plans.pop_back();
@@ -590,7 +600,7 @@ int psi_common(kde_ctx* c, const void* x, int64_t n, int mem_kind, int dtype, in
     if ((st = stage_x(c, x, n, mem_kind, dtype, s, &dx))) return st;
     SampleSpec sp{dx, n, dtype, MODE_PSI, r, g, b, e};
     Plan* p = nullptr;
-    if ((st = get_plan(c, key_single("psi", n, dtype, r, b, e), {sp}, &p))) return st;
+    if ((st = get_plan(c, key_single("psi", n, dtype, r, b, e), {sp}, s, &p))) return st;
     if ((st = run_plan(c, *p, s))) return st;
     if ((st = finish(c, *p, s))) return st;
     *out = p->h_states[0];
@@ -687,7 +697,8 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
 void kde_ctx_destroy(kde_ctx* ctx) {
     if (!ctx) return;
     DeviceGuard dg(ctx->device);
-    (void)hipDeviceSynchronize();
+    // each plan waits for its last replay (and the reset after it) when it is
+    // destroyed; the other calls return only when their work is done
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -773,7 +784,7 @@ int kde_plugin_bandwidth_ex(kde_ctx* c, const void* x, int64_t n, int mem_kind, 
     if ((st = stage_x(c, x, n, mem_kind, dtype, s, &dx))) return out->status = st;
     SampleSpec sp{dx, n, dtype, MODE_PLUGIN, 0, 0.0, 0, -1};
     Plan* p = nullptr;
-    if ((st = get_plan(c, key_single("plugin", n, dtype), {sp}, &p))) return out->status = st;
+    if ((st = get_plan(c, key_single("plugin", n, dtype), {sp}, s, &p))) return out->status = st;
     if ((st = run_plan(c, *p, s))) return out->status = st;
     if ((st = finish(c, *p, s))) return out->status = st;
     fill_result(p->h_states[0], out);
@@ -849,7 +860,7 @@ int kde_plugin_bandwidth_batch(kde_ctx* c, const void* const* xs, const int64_t*
     }
     Plan* p = nullptr;
     int st;
-    if ((st = get_plan(c, key, vs, &p, dout ? &outmap : nullptr))) return st;
+    if ((st = get_plan(c, key, vs, s, &p, dout ? &outmap : nullptr))) return st;
     if (dout) {
         if ((st = run_plan(c, *p, s, dout, false))) return st;
         return ok();

@@ -18,6 +18,8 @@ hipError_t launch_init(State* states, Pub* pubs, int32_t count, uint32_t* ticket
 hipError_t launch_results(const State* states, const int32_t* outmap, int64_t n_out, kde_result* out,
                           hipStream_t s);
 hipError_t launch_persistent(int prec, int R, int grid, hipStream_t s, const LaunchArgs& a);
+// The persistent kernel's instantiation for (precision, R), for graph nodes; nullptr if none.
+const void* persistent_kernel(int prec, int R);
 hipError_t persistent_occupancy(int prec, int R, int* blocks_per_cu);
 }  // namespace kde
 

@@ -55,9 +55,11 @@ def test_plan_cache_beyond_its_capacity(kp):
         assert abs(first[k] - oracle.plugin(xs[k]).h) <= 1e-12 * first[k]
 
 
-def test_contexts_on_several_threads(kp):
-    # one context per thread, all launching at once (ctypes releases the GIL)
-    xs = [synth.draw(synth.DISTS[k % 3], 5000 + 1111 * k, 70 + k) for k in range(6)]
+@pytest.mark.parametrize("rep", range(3))
+def test_contexts_on_several_threads(kp, rep):
+    # one context per thread, all launching at once (ctypes releases the GIL);
+    # new contexts build their plans (and graphs) while the others launch
+    xs = [synth.draw(synth.DISTS[k % 3], 5000 + 1111 * k + rep, 70 + k) for k in range(6)]
     with kp.Context(kp.KDE_FP32_COMP) as c:
         want = [c.plugin_bandwidth(x).h for x in xs]
     got = {}
