@@ -8,6 +8,10 @@
 namespace kde {
 namespace eval {
 
+// Points per tile: one per thread (FP64 plain), 16 per thread (FP32).
+constexpr int kTilePoints64 = 256;
+constexpr int kTilePoints32 = 4096;
+
 struct EvalArgs {
     const void* x;     // samples on the device
     int64_t n;
@@ -19,7 +23,7 @@ struct EvalArgs {
     double s;          // sqrt(log2(e) / 2) / h
     double norm;       // 1 / (n h sqrt(2 pi))
     int64_t W;         // columns per chunk (multiple of 16)
-    int32_t n_rt;      // tiles of 256 points
+    int32_t n_rt;      // tiles of points: 256 (FP64 plain) or 4096 (FP32)
     int32_t n_cc;      // column chunks
     double* part;      // n_cc x m partial sums (n_cc > 1)
     double* out;       // m results on the device
@@ -28,6 +32,9 @@ struct EvalArgs {
 
 // Enqueue the evaluation (and the chunk reduction when n_cc > 1) on s.
 hipError_t launch(const EvalArgs& a, hipStream_t s);
+
+// Blocks of the evaluation kernel for precision prec that one CU holds at once.
+hipError_t blocks_per_cu(int prec, int* out);
 
 }  // namespace eval
 }  // namespace kde

@@ -3,34 +3,55 @@
 //     f(y_k) = (n h)^-1 sum_i phi((y_k - x_i) / h),   k < m,
 // on a grid of points or at the samples themselves.
 //
-// Work decomposition.  The m evaluation points are cut into tiles of 256
-// (one point per thread) and the n samples into chunks of W columns; a
-// block evaluates one (tile, chunk) item, streaming its chunk through LDS in
-// tiles of TJ values read as b128 broadcasts, and writes one partial sum per
-// point.  A second kernel adds a point's partials in a fixed order (so results
-// are deterministic) and applies the normalisation 1 / (n h sqrt(2 pi)).
+// Work decomposition.  The m evaluation points are cut into tiles (256
+// points for FP64, one per thread; 4096 for FP32, 16 consecutive points per
+// thread) and the n samples into chunks of W columns; a block evaluates one
+// (tile, chunk) item, streaming its chunk through LDS in tiles of column
+// values read as b128 broadcasts, and writes one partial sum per point.  A
+// second kernel adds a point's partials in a fixed order (so results are
+// deterministic) and applies the normalisation 1 / (n h sqrt(2 pi)).
 //
-// FP32 arithmetic.  With k = log2(e)/2 and s = sqrt(k) / h, the scaled
-// values v = (x - c) s (computed in FP64, then rounded) give
-//     phi-factor exp(-((y - x)/h)^2 / 2) = 2^(-(v_y - v_x)^2)
-//                                        = 2^(-v_y^2) 2^(v_x (2 v_y) - v_x^2),
-// so with (v_x, -v_x^2) stored per column a pair costs one fma, one
-// v_exp_f32 and an add, and each point's sum is scaled by 2^(-v_y^2) once.
-// The exponent v_y^2 - (v_y - v_x)^2 never exceeds v_y^2, so nothing
-// overflows, and far columns underflow to 0 as they should.  Each
-// group of 32 points (half a wave) has its own centre c, the midrange of its
-// points, and its own FP32 copy of the column tile in LDS, centred on it: the
-// rounding of v_y and of the columns that matter (within a few bandwidths of
-// the group) then stays at a few ulp of small numbers.  A block with a group
-// whose points spread over more than kEvalSpan scaled units (about 9.4 h)
-// takes the difference y - x in FP64 instead (then squares it in FP64 and
-// rounds once before the exp2); this is the case for unsorted evaluation
-// points.  Sorted points and grids up to a spacing of about 0.3 h take the
-// FP32 path.  Each point keeps four FP32 accumulators that
-// take at most kEvalFold terms each, adds them pairwise in FP32 and folds
-// the result into an FP64 sum.  There is no cancellation (every term is
-// positive), so the relative error per point is that of the terms: a few
-// times 1e-7.
+// FP32 arithmetic works in scaled units: with k = log2(e)/2 and
+// s = sqrt(k) / h, v = x s, and the kernel factor exp(-((y - x)/h)^2 / 2) is
+// 2^(-(v_y - v_x)^2).
+//
+// Evenly spaced runs (grids).  When every thread's 16 points are evenly
+// spaced, v_j = u_ref + j ds (j = -8 .. 7 around the run's reference point),
+// a column's 16 terms come from three exp2: with d = u_ref - v_x,
+//     2^(-(d + j ds)^2) = 2^(-K - j^2 ds^2) * E R^j,
+//     E = 2^(K - d^2),  R = 2^(-2 ds d),
+// R^j by repeated multiplication in both directions (R and 1/R), so a pair
+// costs one multiply and one add (an fma and a multiply) instead of an exp2;
+// the factor 2^(-K - j^2 ds^2) is applied once per point at the end.  d is
+// formed in FP64 (exact for the columns that matter whatever the offset of
+// the data) and both exponents are rounded to FP32 once.  The offset K = 24
+// keeps E in FP32's normal range for every column within about 12 scaled
+// units of the reference, so the terms that it would otherwise flush are
+// below 2^-100 of a nearby sample's; the span of a run is limited to 4
+// scaled units (points at most 8 steps from the reference), which bounds
+// the terms (at most 2^(K + 4)) and the error of R^j.  A thread's FP32 sums
+// take kRunFold columns before they are folded into FP64.  The derivation
+// of the error bound (about 6e-6 relative per point, measured 1e-7) is in
+// the tests of this kernel.
+//
+// Other points (unsorted, uneven, or spaced more widely than 0.3 h) take the
+// per-point path in sub-tiles of 256: for 2^(-(v_y - v_x)^2) =
+// 2^(-v_y^2) 2^(v_x (2 v_y) - v_x^2), with (v_x, -v_x^2) stored per column a
+// pair costs one fma, one v_exp_f32 and an add, and each point's sum is
+// scaled by 2^(-v_y^2) once.  The exponent v_y^2 - (v_y - v_x)^2 never
+// exceeds v_y^2, so nothing overflows, and far columns underflow to 0 as
+// they should.  Each group of 32 points (half a wave) has its own centre c,
+// the midrange of its points, and its own FP32 copy of the column tile in
+// LDS, centred on it: the rounding of v_y and of the columns that matter
+// (within a few bandwidths of the group) then stays at a few ulp of small
+// numbers.  A sub-tile with a group whose points spread over more than
+// kEvalSpan scaled units (about 9.4 h) takes the difference y - x in FP64
+// instead (then squares it in FP64 and rounds once before the exp2); this
+// is the case for unsorted evaluation points.  Each point keeps four FP32
+// accumulators that take at most kEvalFold terms each, adds them pairwise
+// in FP32 and folds the result into an FP64 sum.  There is no cancellation
+// (every term is positive), so the relative error per point is that of the
+// terms: a few times 1e-7.
 //
 // FP64 arithmetic is the plain definition: u = (y - x) / h, exp(-u^2 / 2).
 #include <hip/hip_runtime.h>
@@ -50,6 +71,17 @@ constexpr int NGROUP = BLOCK / GROUP;
 constexpr int TJN = 256;        // columns per LDS tile and group (FP32 path; two floats each)
 constexpr int kEvalFold = 4;    // b128 reads per FP32 accumulator before the FP64 fold
 constexpr double kEvalSpan = 8.0;
+constexpr int RUN = 16;              // points per thread in an FP32 tile
+constexpr int RUN_REF = 8;           // the run's reference point
+constexpr int TP32 = BLOCK * RUN;    // points per FP32 tile
+static_assert(TP32 == kTilePoints32 && BLOCK == kTilePoints64, "tile sizes the host assumes");
+static_assert(NGROUP * TJN >= TJ, "the FP64 column tile fits the group tiles");
+constexpr double kRunTol = 1e-9;     // evenly spaced to this many scaled units
+constexpr double kRunSpan = 4.0;     // largest span of a run, scaled units
+constexpr double kRunK = 24.0;       // exponent offset of the run terms
+constexpr float kRunArgMax = 60.0f;  // clamp of the ratio's exponent
+constexpr double kRunPad = 1e30;     // column value of a padded (or non-finite) sample
+constexpr int kRunFold = 32;         // columns per FP32 run accumulator before the FP64 fold
 
 __device__ __forceinline__ double load_x(const void* x, int32_t dtype, int64_t i) {
     return dtype == 0 ? static_cast<const double*>(x)[i] : static_cast<double>(static_cast<const float*>(x)[i]);
@@ -82,20 +114,134 @@ __device__ __forceinline__ void flag_nonfinite(int32_t* flag) {
     __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One (tile, chunk) item.  PREC 0: FP64 plain; 1: FP32 (centred, or FP64
-// differences for a wide tile).
-template <int PREC>
-__global__ __launch_bounds__(BLOCK) void k_eval(EvalArgs a) {
-    // FP64 plain: one FP64 tile; FP32: NGROUP FP32 tiles of TJN, or (wide
-    // blocks) one FP64 tile of TJ in the same memory
-    constexpr int kLdsDoubles = PREC == 0 ? TJ : NGROUP * TJN;
-    static_assert(PREC == 0 || kLdsDoubles >= TJ, "the FP64 tile fits the group tiles");
-    __shared__ __align__(16) double tile64[kLdsDoubles];
-    __shared__ double red[2 * BLOCK / 64];
-    __shared__ double gcen[NGROUP];
-    __shared__ int32_t gwide;
-    float* tile32 = reinterpret_cast<float*>(tile64);
+// FP32, one 256-point sub-tile of an item whose points are not evenly spaced
+// runs: point k_first + tid against columns [c0, c1), centred per group of 32
+// points (narrow groups) or with FP64 differences (wide blocks).
+__device__ void eval_subtile_f32(const EvalArgs& a, int32_t cc, int64_t k_first, int64_t c0, int64_t c1,
+                                 double* tile64, double* red, double* gcen, int32_t* gwide) {
+    const int tid = threadIdx.x;
+    const int64_t k = k_first + tid;
+    const bool live = k < a.m;
+    double y = live ? a.y[k] : 0.0;
+    if (live && !isfinite(y)) {
+        flag_nonfinite(a.flag);
+        y = 0.0;
+    }
+    double tot = 0.0;
+    // centre and spread of each group of 32 points (lanes 0-31 and 32-63
+    // of a wave); a group without live points is narrow
+    double glo = live ? y : INFINITY, ghi = live ? y : -INFINITY;
+#pragma unroll
+    for (int off = GROUP / 2; off > 0; off >>= 1) {
+        glo = fmin(glo, __shfl_xor(glo, off, 64));
+        ghi = fmax(ghi, __shfl_xor(ghi, off, 64));
+    }
+    const int grp = tid / GROUP;
+    __syncthreads();  // the previous sub-tile is done with gcen, gwide and the tiles
+    if (tid == 0) *gwide = 0;
+    __syncthreads();
+    if ((tid & (GROUP - 1)) == 0) {
+        const bool any = glo <= ghi;
+        gcen[grp] = any ? 0.5 * glo + 0.5 * ghi : 0.0;
+        if (any && (ghi - glo) * a.s > kEvalSpan) atomicOr(gwide, 1);
+    }
+    __syncthreads();
+    const bool narrow = *gwide == 0;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (narrow) {
+        // 2^(-(v_y - v_x)^2) = 2^(-v_y^2) 2^(fma(v_x, 2 v_y, -v_x^2)): the
+        // column tile holds (v_x, -v_x^2), the argument is at most v_y^2
+        // (<= 16 here), and the point's factor 2^(-v_y^2) is applied once
+        // at the end in FP64, so a pair costs an fma, the exp2 and an add
+        const float vy = (float)((y - gcen[grp]) * a.s);
+        const float vy2 = 2.0f * vy;
+        float2* tile2 = reinterpret_cast<float2*>(tile64);
+        const float4* t4 = reinterpret_cast<const float4*>(tile2 + grp * TJN);
+        for (int64_t cj = c0; cj < c1; cj += TJN) {
+            const int len = (int)min((int64_t)TJN, c1 - cj);
+            __syncthreads();
+            for (int e = tid; e < TJN; e += BLOCK) {
+                double v = 0.0;
+                bool pad = true;
+                if (e < len) {
+                    v = load_x(a.x, a.dtype, cj + e);
+                    if (!isfinite(v))
+                        flag_nonfinite(a.flag);
+                    else
+                        pad = false;
+                }
+#pragma unroll
+                for (int g = 0; g < NGROUP; ++g) {
+                    // a column too far away for v_x^2 to stay finite contributes 0
+                    const double vxd = (v - gcen[g]) * a.s;
+                    const bool zero = pad || !(fabs(vxd) < 1e15);
+                    const float vx = zero ? 0.0f : (float)vxd;
+                    tile2[g * TJN + e] = make_float2(vx, zero ? -INFINITY : -(vx * vx));
+                }
+            }
+            __syncthreads();
+            const int groups = (len + 4 * kEvalFold - 1) / (4 * kEvalFold);
+            for (int g = 0; g < groups; ++g) {
+#pragma unroll
+                for (int q = 0; q < 2 * kEvalFold; ++q) {
+                    const float4 v = t4[g * 2 * kEvalFold + q];
+                    acc[(2 * q) & 3] += __builtin_amdgcn_exp2f(__builtin_fmaf(v.x, vy2, v.y));
+                    acc[(2 * q + 1) & 3] += __builtin_amdgcn_exp2f(__builtin_fmaf(v.z, vy2, v.w));
+                }
+                tot += (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
+                acc[0] = acc[1] = acc[2] = acc[3] = 0.0f;
+            }
+        }
+        tot *= exp2(-((double)vy * (double)vy));
+    } else {
+        // one centre for the block, differences in FP64
+        double hi;
+        const double lo = block_min_max(live ? y : INFINITY, live ? y : -INFINITY, red, &hi);
+        const double c = 0.5 * lo + 0.5 * hi;
+        const double uy = (y - c) * a.s;
+        for (int64_t cj = c0; cj < c1; cj += TJ) {
+            const int len = (int)min((int64_t)TJ, c1 - cj);
+            __syncthreads();
+            for (int e = tid; e < TJ; e += BLOCK) {
+                double v = INFINITY;
+                if (e < len) {
+                    v = load_x(a.x, a.dtype, cj + e);
+                    if (!isfinite(v)) {
+                        flag_nonfinite(a.flag);
+                        v = INFINITY;
+                    } else {
+                        v = (v - c) * a.s;
+                    }
+                }
+                tile64[e] = v;
+            }
+            __syncthreads();
+            const int groups = (len + 4 * kEvalFold - 1) / (4 * kEvalFold);
+            const double2* t2 = reinterpret_cast<const double2*>(tile64);
+            for (int g = 0; g < groups; ++g) {
+#pragma unroll
+                for (int q = 0; q < 2 * kEvalFold; ++q) {
+                    const double2 v = t2[g * 2 * kEvalFold + q];
+                    const double d0 = uy - v.x, d1 = uy - v.y;
+                    acc[(2 * q) & 3] += __builtin_amdgcn_exp2f(-(float)(d0 * d0));
+                    acc[(2 * q + 1) & 3] += __builtin_amdgcn_exp2f(-(float)(d1 * d1));
+                }
+                tot += (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
+                acc[0] = acc[1] = acc[2] = acc[3] = 0.0f;
+            }
+        }
+    }
+    if (live) {
+        if (a.n_cc == 1)
+            a.out[k] = tot * a.norm;
+        else
+            a.part[(int64_t)cc * a.m + k] = tot;
+    }
+}
 
+// One (tile, chunk) item, FP64 plain: a tile of 256 points, one per thread.
+__global__ __launch_bounds__(BLOCK) void k_eval64(EvalArgs a) {
+    __shared__ __align__(16) double tile64[TJ];
     const int tid = threadIdx.x;
     const int32_t rt = (int32_t)(blockIdx.x / a.n_cc);
     const int32_t cc = (int32_t)(blockIdx.x % a.n_cc);
@@ -108,135 +254,29 @@ __global__ __launch_bounds__(BLOCK) void k_eval(EvalArgs a) {
     }
     const int64_t c0 = (int64_t)cc * a.W;
     const int64_t c1 = min(c0 + a.W, a.n);
-
+    const double inv_h = 1.0 / a.h;
     double tot = 0.0;
-    if constexpr (PREC == 0) {
-        const double inv_h = 1.0 / a.h;
-        for (int64_t cj = c0; cj < c1; cj += TJ) {
-            const int len = (int)min((int64_t)TJ, c1 - cj);
-            __syncthreads();
-            for (int e = tid; e < TJ; e += BLOCK) {
-                double v = INFINITY;
-                if (e < len) {
-                    v = load_x(a.x, a.dtype, cj + e);
-                    if (!isfinite(v)) {
-                        flag_nonfinite(a.flag);
-                        v = INFINITY;
-                    }
-                }
-                tile64[e] = v;
-            }
-            __syncthreads();
-            const double2* t2 = reinterpret_cast<const double2*>(tile64);
-            for (int j = 0; j < len; j += 2) {
-                const double2 v = t2[j >> 1];
-                const double u0 = (y - v.x) * inv_h, u1 = (y - v.y) * inv_h;
-                tot += exp(-0.5 * u0 * u0);
-                tot += exp(-0.5 * u1 * u1);
-            }
-        }
-    } else {
-        // centre and spread of each group of 32 points (lanes 0-31 and 32-63
-        // of a wave); a group without live points is narrow
-        double glo = live ? y : INFINITY, ghi = live ? y : -INFINITY;
-#pragma unroll
-        for (int off = GROUP / 2; off > 0; off >>= 1) {
-            glo = fmin(glo, __shfl_xor(glo, off, 64));
-            ghi = fmax(ghi, __shfl_xor(ghi, off, 64));
-        }
-        const int grp = tid / GROUP;
-        if (tid == 0) gwide = 0;
+    for (int64_t cj = c0; cj < c1; cj += TJ) {
+        const int len = (int)min((int64_t)TJ, c1 - cj);
         __syncthreads();
-        if ((tid & (GROUP - 1)) == 0) {
-            const bool any = glo <= ghi;
-            gcen[grp] = any ? 0.5 * glo + 0.5 * ghi : 0.0;
-            if (any && (ghi - glo) * a.s > kEvalSpan) atomicOr(&gwide, 1);
+        for (int e = tid; e < TJ; e += BLOCK) {
+            double v = INFINITY;
+            if (e < len) {
+                v = load_x(a.x, a.dtype, cj + e);
+                if (!isfinite(v)) {
+                    flag_nonfinite(a.flag);
+                    v = INFINITY;
+                }
+            }
+            tile64[e] = v;
         }
         __syncthreads();
-        const bool narrow = gwide == 0;
-        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (narrow) {
-            // 2^(-(v_y - v_x)^2) = 2^(-v_y^2) 2^(fma(v_x, 2 v_y, -v_x^2)): the
-            // column tile holds (v_x, -v_x^2), the argument is at most v_y^2
-            // (<= 16 here), and the point's factor 2^(-v_y^2) is applied once
-            // at the end in FP64, so a pair costs an fma, the exp2 and an add
-            const float vy = (float)((y - gcen[grp]) * a.s);
-            const float vy2 = 2.0f * vy;
-            float2* tile2 = reinterpret_cast<float2*>(tile64);
-            const float4* t4 = reinterpret_cast<const float4*>(tile2 + grp * TJN);
-            for (int64_t cj = c0; cj < c1; cj += TJN) {
-                const int len = (int)min((int64_t)TJN, c1 - cj);
-                __syncthreads();
-                for (int e = tid; e < TJN; e += BLOCK) {
-                    double v = 0.0;
-                    bool pad = true;
-                    if (e < len) {
-                        v = load_x(a.x, a.dtype, cj + e);
-                        if (!isfinite(v))
-                            flag_nonfinite(a.flag);
-                        else
-                            pad = false;
-                    }
-#pragma unroll
-                    for (int g = 0; g < NGROUP; ++g) {
-                        // a column too far away for v_x^2 to stay finite contributes 0
-                        const double vxd = (v - gcen[g]) * a.s;
-                        const bool zero = pad || !(fabs(vxd) < 1e15);
-                        const float vx = zero ? 0.0f : (float)vxd;
-                        tile2[g * TJN + e] = make_float2(vx, zero ? -INFINITY : -(vx * vx));
-                    }
-                }
-                __syncthreads();
-                const int groups = (len + 4 * kEvalFold - 1) / (4 * kEvalFold);
-                for (int g = 0; g < groups; ++g) {
-#pragma unroll
-                    for (int q = 0; q < 2 * kEvalFold; ++q) {
-                        const float4 v = t4[g * 2 * kEvalFold + q];
-                        acc[(2 * q) & 3] += __builtin_amdgcn_exp2f(__builtin_fmaf(v.x, vy2, v.y));
-                        acc[(2 * q + 1) & 3] += __builtin_amdgcn_exp2f(__builtin_fmaf(v.z, vy2, v.w));
-                    }
-                    tot += (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
-                    acc[0] = acc[1] = acc[2] = acc[3] = 0.0f;
-                }
-            }
-            tot *= exp2(-((double)vy * (double)vy));
-        } else {
-            // one centre for the block, differences in FP64
-            double hi;
-            const double lo = block_min_max(live ? y : INFINITY, live ? y : -INFINITY, red, &hi);
-            const double c = 0.5 * lo + 0.5 * hi;
-            const double uy = (y - c) * a.s;
-            for (int64_t cj = c0; cj < c1; cj += TJ) {
-                const int len = (int)min((int64_t)TJ, c1 - cj);
-                __syncthreads();
-                for (int e = tid; e < TJ; e += BLOCK) {
-                    double v = INFINITY;
-                    if (e < len) {
-                        v = load_x(a.x, a.dtype, cj + e);
-                        if (!isfinite(v)) {
-                            flag_nonfinite(a.flag);
-                            v = INFINITY;
-                        } else {
-                            v = (v - c) * a.s;
-                        }
-                    }
-                    tile64[e] = v;
-                }
-                __syncthreads();
-                const int groups = (len + 4 * kEvalFold - 1) / (4 * kEvalFold);
-                const double2* t2 = reinterpret_cast<const double2*>(tile64);
-                for (int g = 0; g < groups; ++g) {
-#pragma unroll
-                    for (int q = 0; q < 2 * kEvalFold; ++q) {
-                        const double2 v = t2[g * 2 * kEvalFold + q];
-                        const double d0 = uy - v.x, d1 = uy - v.y;
-                        acc[(2 * q) & 3] += __builtin_amdgcn_exp2f(-(float)(d0 * d0));
-                        acc[(2 * q + 1) & 3] += __builtin_amdgcn_exp2f(-(float)(d1 * d1));
-                    }
-                    tot += (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
-                    acc[0] = acc[1] = acc[2] = acc[3] = 0.0f;
-                }
-            }
+        const double2* t2 = reinterpret_cast<const double2*>(tile64);
+        for (int j = 0; j < len; j += 2) {
+            const double2 v = t2[j >> 1];
+            const double u0 = (y - v.x) * inv_h, u1 = (y - v.y) * inv_h;
+            tot += exp(-0.5 * u0 * u0);
+            tot += exp(-0.5 * u1 * u1);
         }
     }
     if (live) {
@@ -247,13 +287,143 @@ __global__ __launch_bounds__(BLOCK) void k_eval(EvalArgs a) {
     }
 }
 
+// One step of an evenly spaced run: column v_x (scaled, centred) against the
+// lane's RUN points v_j = u_ref + j ds, j = i - RUN_REF.  With d = u_ref - v_x,
+//     -(d + j ds)^2 = -d^2 - 2 j ds d - j^2 ds^2,
+// so 2^(K - (d + j ds)^2 + j^2 ds^2) = E R^j with E = 2^(K - d^2) and
+// R = 2^(-2 ds d): three exp2 per column, then one multiply and one add per
+// point; the factor 2^(-K - j^2 ds^2) is applied to the point's sum at the
+// end.  Both exponents are formed in FP64 and rounded once; the R exponent is
+// clamped to +-kRunArgMax, which only changes columns whose E is 0.
+__device__ __forceinline__ void run_step(double vx, double u_ref, double m2ds, float (&acc)[RUN]) {
+    const double d = u_ref - vx;
+    const float ea = (float)__builtin_fma(-d, d, kRunK);
+    const float ra = __builtin_amdgcn_fmed3f((float)(d * m2ds), -kRunArgMax, kRunArgMax);
+    const float e = __builtin_amdgcn_exp2f(ea);
+    const float r = __builtin_amdgcn_exp2f(ra);
+    const float ri = __builtin_amdgcn_exp2f(-ra);
+    acc[RUN_REF] += e;
+    float t = e;
+#pragma unroll
+    for (int j = 1; j < RUN - RUN_REF; ++j) {
+        t *= r;
+        acc[RUN_REF + j] += t;
+    }
+    t = e;
+#pragma unroll
+    for (int j = 1; j <= RUN_REF; ++j) {
+        t *= ri;
+        acc[RUN_REF - j] += t;
+    }
+}
+
+// One (tile, chunk) item, FP32: a tile of RUN * 256 points, RUN consecutive
+// points per thread.  If every thread's points are an evenly spaced run (to
+// kRunTol scaled units, spanning at most kRunSpan) the block takes the run
+// path; otherwise it evaluates the tile as RUN sub-tiles of 256 points, one
+// point per thread.
+__global__ __launch_bounds__(BLOCK) void k_eval32(EvalArgs a) {
+    __shared__ __align__(16) double tile64[NGROUP * TJN];
+    __shared__ double red[2 * BLOCK / 64];
+    __shared__ double gcen[NGROUP];
+    __shared__ int32_t gwide;
+
+    const int tid = threadIdx.x;
+    const int32_t rt = (int32_t)(blockIdx.x / a.n_cc);
+    const int32_t cc = (int32_t)(blockIdx.x % a.n_cc);
+    const int64_t kb = (int64_t)rt * TP32;
+    const int64_t c0 = (int64_t)cc * a.W;
+    const int64_t c1 = min(c0 + a.W, a.n);
+
+    // this thread's points k0 .. k0 + live_n - 1: an evenly spaced run?
+    const int64_t k0 = kb + (int64_t)tid * RUN;
+    const int live_n = (int)max((int64_t)0, min((int64_t)RUN, a.m - k0));
+    bool ok = true;
+    double y0 = 0.0, dy = 0.0;
+    if (live_n > 0) {
+        y0 = a.y[k0];
+        if (live_n > 1) dy = (a.y[k0 + live_n - 1] - y0) / (double)(live_n - 1);
+        for (int i = 0; i < live_n; ++i) {
+            const double yi = a.y[k0 + i];
+            if (!isfinite(yi)) {
+                flag_nonfinite(a.flag);
+                ok = false;
+            } else if (!(fabs((yi - (y0 + (double)i * dy)) * a.s) <= kRunTol)) {
+                ok = false;
+            }
+        }
+        if (!(fabs(dy * a.s) * (double)(RUN - 1) <= kRunSpan)) ok = false;
+    }
+    if (!__syncthreads_and(ok)) {
+        for (int sub = 0; sub < RUN; ++sub) {
+            const int64_t kf = kb + (int64_t)sub * BLOCK;
+            if (kf >= a.m) break;  // the same for every thread
+            eval_subtile_f32(a, cc, kf, c0, c1, tile64, red, gcen, &gwide);
+        }
+        return;
+    }
+
+    // run path: columns centred on the block's first point, in FP64
+    const double cb = a.y[kb];
+    const double ds = dy * a.s;
+    const double u_ref = (y0 - cb) * a.s + (double)RUN_REF * ds;
+    const double m2ds = -2.0 * ds;
+    double tot[RUN];
+#pragma unroll
+    for (int i = 0; i < RUN; ++i) tot[i] = 0.0;
+    const double2* t2 = reinterpret_cast<const double2*>(tile64);
+    for (int64_t cj = c0; cj < c1; cj += TJ) {
+        const int len = (int)min((int64_t)TJ, c1 - cj);
+        __syncthreads();
+        for (int e = tid; e < TJ; e += BLOCK) {
+            double v = kRunPad;
+            if (e < len) {
+                const double x = load_x(a.x, a.dtype, cj + e);
+                if (!isfinite(x))
+                    flag_nonfinite(a.flag);
+                else
+                    v = (x - cb) * a.s;
+            }
+            tile64[e] = v;
+        }
+        __syncthreads();
+        const int groups = (len + kRunFold - 1) / kRunFold;
+        for (int g = 0; g < groups; ++g) {
+            float acc[RUN];
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) acc[i] = 0.0f;
+#pragma unroll
+            for (int q = 0; q < kRunFold / 2; ++q) {
+                const double2 v = t2[g * (kRunFold / 2) + q];
+                run_step(v.x, u_ref, m2ds, acc);
+                run_step(v.y, u_ref, m2ds, acc);
+            }
+#pragma unroll
+            for (int i = 0; i < RUN; ++i) tot[i] += (double)acc[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RUN; ++i) {
+        if (i < live_n) {
+            const double j = (double)(i - RUN_REF);
+            const double t = tot[i] * exp2(-(double)kRunK - j * j * ds * ds);
+            if (a.n_cc == 1)
+                a.out[k0 + i] = t * a.norm;
+            else
+                a.part[(int64_t)cc * a.m + k0 + i] = t;
+        }
+    }
+}
+
 // out[k] = norm * sum over chunks in a fixed order: RLANES threads per point,
-// lane q adding chunks q, q + RLANES, q + 2 RLANES, ... in order, then lane 0
-// adding the RLANES lane sums in lane order (deterministic).  Consecutive
-// threads take consecutive points, so each load instruction reads whole
-// lines of one chunk's partials.
+// lane q adding chunks q + RLANES (RILP i + r) into its r-th sum (RILP sums in
+// flight, so a thread keeps RILP loads outstanding), the sums then added in
+// order r = 0, 1, ..., and lane 0 adding the RLANES lane sums in lane order
+// (deterministic).  Consecutive threads take consecutive points, so each load
+// instruction reads whole lines of one chunk's partials.
 constexpr int RLANES = 16;
 constexpr int RPOINTS = BLOCK / RLANES;
+constexpr int RILP = 8;
 
 __global__ __launch_bounds__(BLOCK) void k_eval_reduce(const double* part, int32_t n_cc, int64_t m, double norm,
                                                        double* out) {
@@ -261,8 +431,21 @@ __global__ __launch_bounds__(BLOCK) void k_eval_reduce(const double* part, int32
     const int p = threadIdx.x % RPOINTS, q = threadIdx.x / RPOINTS;
     const int64_t k = (int64_t)blockIdx.x * RPOINTS + p;
     double s = 0.0;
-    if (k < m)
-        for (int32_t c = q; c < n_cc; c += RLANES) s += part[(int64_t)c * m + k];
+    if (k < m) {
+        double r[RILP];
+#pragma unroll
+        for (int i = 0; i < RILP; ++i) r[i] = 0.0;
+        int32_t c = q;
+        for (; c + (RILP - 1) * RLANES < n_cc; c += RILP * RLANES) {
+#pragma unroll
+            for (int i = 0; i < RILP; ++i) r[i] += part[(int64_t)(c + i * RLANES) * m + k];
+        }
+#pragma unroll
+        for (int i = 0; i < RILP; ++i)
+            if (c + i * RLANES < n_cc) r[i] += part[(int64_t)(c + i * RLANES) * m + k];
+#pragma unroll
+        for (int i = 0; i < RILP; ++i) s += r[i];
+    }
     red[q][p] = s;
     __syncthreads();
     if (q == 0 && k < m) {
@@ -276,14 +459,19 @@ __global__ __launch_bounds__(BLOCK) void k_eval_reduce(const double* part, int32
 hipError_t launch(const EvalArgs& a, hipStream_t s) {
     const int64_t items = (int64_t)a.n_rt * a.n_cc;
     if (a.prec == 0)
-        hipLaunchKernelGGL(k_eval<0>, dim3((unsigned)items), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_eval64, dim3((unsigned)items), dim3(BLOCK), 0, s, a);
     else
-        hipLaunchKernelGGL(k_eval<1>, dim3((unsigned)items), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_eval32, dim3((unsigned)items), dim3(BLOCK), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.n_cc == 1) return e;
     const unsigned blocks = (unsigned)((a.m + RPOINTS - 1) / RPOINTS);
     hipLaunchKernelGGL(k_eval_reduce, dim3(blocks), dim3(BLOCK), 0, s, a.part, a.n_cc, a.m, a.norm, a.out);
     return hipGetLastError();
+}
+
+hipError_t blocks_per_cu(int prec, int* out) {
+    return prec == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_eval64, BLOCK, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_eval32, BLOCK, 0);
 }
 
 }  // namespace eval

@@ -927,8 +927,11 @@ int kde_eval_ex(kde_ctx* c, const void* x, int64_t n, int mem_kind, int dtype, c
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard dg(c->device);
 
-    // tiles of 256 points times chunks of W samples: at least ~4096 items, at
-    // most 2^24 pairs per item, chunks of at least 1024 samples
+    // tiles of points times chunks of W samples.  FP64 plain: tiles of 256
+    // points, at least ~4096 items, at most 2^24 pairs per item, chunks of at
+    // least 1024 samples.  FP32: tiles of 4096 points, items of at most 2^26
+    // pairs, as many as fill whole rounds of the blocks the GPU holds at once
+    // (the items of a round take equal time), chunks of at least 512 samples
     eval::EvalArgs a{};
     a.n = n;
     a.m = m;
@@ -937,9 +940,25 @@ int kde_eval_ex(kde_ctx* c, const void* x, int64_t n, int mem_kind, int dtype, c
     a.h = h;
     a.s = std::sqrt(0.5 * 1.4426950408889634) / h;
     a.norm = 1.0 / ((double)n * h * std::sqrt(2.0 * 3.14159265358979323846));
-    const int64_t n_rt = (m + 255) / 256;
-    int64_t n_cc = std::max<int64_t>((4096 + n_rt - 1) / n_rt, (256 * n + ((int64_t)1 << 24) - 1) >> 24);
-    n_cc = std::max<int64_t>(1, std::min<int64_t>(n_cc, (n + 1023) / 1024));
+    const bool f32 = a.prec != 0;
+    const int64_t tp = f32 ? eval::kTilePoints32 : eval::kTilePoints64;
+    const int64_t wmin = f32 ? 512 : 1024;
+    const int lg_pairs = f32 ? 26 : 24;
+    const int64_t n_rt = (m + tp - 1) / tp;
+    int64_t n_cc = (tp * n + ((int64_t)1 << lg_pairs) - 1) >> lg_pairs;
+    if (!f32) {
+        n_cc = std::max<int64_t>(n_cc, (4096 + n_rt - 1) / n_rt);
+    } else {
+        if (c->eval32_resident == 0) {
+            int bpc = 0;
+            HIPCHK(eval::blocks_per_cu(1, &bpc));
+            c->eval32_resident = (int64_t)std::max(1, bpc) * c->cus;
+        }
+        const int64_t res = c->eval32_resident;
+        const int64_t rounds = (n_rt * n_cc + res - 1) / res;
+        n_cc = std::max<int64_t>(n_cc, (rounds * res + n_rt - 1) / n_rt);
+    }
+    n_cc = std::max<int64_t>(1, std::min<int64_t>(n_cc, (n + wmin - 1) / wmin));
     a.W = ((((n + n_cc - 1) / n_cc) + 15) / 16) * 16;
     n_cc = (n + a.W - 1) / a.W;
     if (n_rt * n_cc > ((int64_t)1 << 31) - 1) return set_err(KDE_EINVAL, "too many evaluation items");

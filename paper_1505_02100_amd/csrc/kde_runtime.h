@@ -143,6 +143,7 @@ struct kde_ctx {
     size_t max_plans = 16;
     kde::rt::DevBuf x_stage;                  // host samples copied here
     kde::rt::DevBuf ev_y, ev_out, ev_part, ev_flag;  // density evaluation buffers
+    int64_t eval32_resident = 0;              // FP32 evaluation blocks the device holds at once (0: not yet asked)
 };
 
 namespace kde {

@@ -14,6 +14,15 @@ at most 4.4e-6 + 5.4e-6 + 1e-7, below 1e-5; wide groups take the
 differences in FP64 (only the square's and exp2's rounding, a few u32 times
 d^2).  The sums of positive terms add a few u32.  Points where the density is
 below 1e-30 of its maximum (terms below FP32's range) are not compared.
+
+Evenly spaced runs (16 consecutive points a thread, spacing ds <= 4/15 scaled
+units): with d = u_ref - v_x formed in FP64, point j's term is
+2^(-K - j^2 ds^2) E R^j with E = 2^(fl(K - d^2)), R = 2^(fl(-2 ds d)), K = 24,
+and R^j taken by |j| <= 8 FP32 multiplications.  Over the terms that matter
+(|d + j ds| <= 5, so |d| <= 7.2): ln2 u32 |K - d^2| <= 19 u32 from E's
+exponent, per step ln2 u32 |2 ds d| + 2 u32 (exp2) + u32 (multiply) <= 5.6 u32,
+so 45 u32 over 8 steps, and 31 u32 from FP32 sums of 32 terms: about 97 u32 =
+5.8e-6 in all, below 1e-5.
 """
 import math
 
@@ -136,3 +145,60 @@ def test_errors_and_empty(kp, ctxs):
     # the literal call: default FP64 context, host arrays
     y = np.linspace(-2, 2, 9)
     np.testing.assert_allclose(kp.kde_eval(x, y, 0.4), oracle.kde_eval(x, 0.4, y), rtol=1e-13)
+
+
+def _rel(got, ref):
+    keep = ref > 1e-30 * ref.max()
+    return np.max(np.abs(got[keep] - ref[keep]) / ref[keep])
+
+
+def test_evenly_spaced_runs_and_their_fallbacks(kp, ctxs):
+    # FP32 tiles of 4096 points take the run path when every thread's 16
+    # points are evenly spaced and span at most 4 scaled units, and the
+    # per-point path otherwise; every case against the oracle, ragged tails
+    # included
+    c32, c64 = ctxs[kp.KDE_FP32_COMP], ctxs[kp.KDE_FP64_PLAIN]
+    x = synth.draw("bimodal", 30000, 31)
+    h = 0.05
+    lo, hi = x.min() - 1.0, x.max() + 1.0
+    cases = {
+        "ascending, ragged": np.linspace(lo, hi, 2 * 4096 + 17),
+        "descending": np.linspace(hi, lo, 5000),
+        "constant": np.full(40, 0.3),
+        "one point": np.array([0.25]),
+        "too coarse for a run": np.linspace(lo, hi, 300),
+        # two spacings: the thread whose run straddles the seam fails the
+        # check and its block falls back; other blocks keep the run path
+        "piecewise": np.concatenate([np.linspace(lo, 0.0, 4096 + 9, endpoint=False), np.linspace(0.0, hi, 7000)]),
+        "perturbed point": np.linspace(lo, hi, 9000) + np.where(np.arange(9000) == 4100, 1e-7, 0.0),
+    }
+    for name, y in cases.items():
+        ref = oracle.kde_eval(x, h, y)
+        assert _rel(c32.eval(x, y, h), ref) <= FP32_TOL, name
+        assert _rel(c64.eval(x, y, h), ref) <= 2 * x.size * U + 4 * U, name
+
+
+def test_runs_far_from_the_data(kp, ctxs):
+    # a grid whose points lie 6 to 10 bandwidths from the nearest of a few
+    # samples: the densities are tiny but well inside FP32's range after the
+    # exponent offset, and compared like all others above 1e-30 of the largest
+    x = np.array([0.0, 0.01, -0.02, 0.015])
+    h = 0.1
+    y = np.linspace(0.6, 1.0, 4096 + 100)
+    ref = oracle.kde_eval(x, h, y)
+    got = ctxs[kp.KDE_FP32_COMP].eval(x, y, h)
+    assert ref.min() > 1e-30 * ref.max()
+    assert _rel(got, ref) <= FP32_TOL
+
+
+def test_runs_are_deterministic_and_flag_nonfinite_points(kp, ctxs):
+    c = ctxs[kp.KDE_FP32_COMP]
+    x = synth.normal(40000, 8)
+    y = np.linspace(-4, 4, 12000)
+    a, b = c.eval(x, y, 0.07), c.eval(x, y, 0.07)
+    assert np.array_equal(a, b)
+    bad = y.copy()
+    bad[5000] = math.inf
+    with pytest.raises(kp.KdeError) as e:
+        c.eval(x, bad, 0.07)
+    assert e.value.code == kp.KDE_ENONFINITE
