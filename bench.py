@@ -263,7 +263,8 @@ def bench_eval(args):
            "device_ms": {q: round(float(np.percentile(dev, p)), 4) for q, p in (("p10", 10), ("p50", 50), ("p90", 90))},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                        "kernel": "kde::eval::k_eval", "kernel_ms_avg": round(dev_ms, 4),
+                        "kernel": ("kde::eval::k_eval64" if args.precision == "fp64" else "kde::eval::k_eval32") + " + k_eval_reduce",
+                        "kernel_ms_avg": round(dev_ms, 4),
                         "flop_per_launch": EVAL_FLOP_PER_PAIR * pairs}}
     if not args.no_cpu_baseline:
         import oracle
