@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -49,6 +50,8 @@ std::vector<double> normal_sample(int64_t n, uint64_t seed) {
     }
     return x;
 }
+
+constexpr int kWarmupMs = 300;  // load before the first timed candidate
 
 // Median device time (ms) of `reps` selections on a context, or -1 on error.
 double time_ctx(kde_ctx* c, const void* dx, int64_t n, int reps) {
@@ -129,6 +132,25 @@ extern "C" int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t c
         if (hipMalloc(&dx[q], h.size() * 8) != hipSuccess ||
             hipMemcpy(dx[q], h.data(), h.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
             st = KDE_EDEVICE;
+    }
+    // bring the GPU to its clock under load before anything is timed: the first
+    // tens of milliseconds of load run at a lower clock, which made the first
+    // candidates look slower than later ones
+    if (st == KDE_OK) {
+        kde_ctx* w = nullptr;
+        if (kde_ctx_create(&w, &base) == KDE_OK) {
+            size_t big = 0;
+            for (size_t q = 1; q < sizes.size(); ++q)
+                if (sizes[q] > sizes[big]) big = q;
+            const auto t0 = std::chrono::steady_clock::now();
+            kde_result r;
+            for (int k = 0; k < 100000; ++k) {
+                if (kde_plugin_bandwidth_ex(w, dx[big], sizes[big], KDE_MEM_DEVICE, KDE_F64, nullptr, &r) != KDE_OK)
+                    break;
+                if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(kWarmupMs)) break;
+            }
+            kde_ctx_destroy(w);
+        }
     }
     const int Rs[] = {1, 2, 4};
     // the FP32 precision also tries the polynomial exponential (its kernels are
