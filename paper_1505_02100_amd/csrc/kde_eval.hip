@@ -81,6 +81,7 @@ constexpr double kRunSpan = 4.0;     // largest span of a run, scaled units
 constexpr double kRunK = 24.0;       // exponent offset of the run terms
 constexpr float kRunArgMax = 60.0f;  // clamp of the ratio's exponent
 constexpr double kRunPad = 1e30;     // column value of a padded (or non-finite) sample
+constexpr double kRunRefMax = 1048576.0;  // largest |reference| of a run, scaled units
 constexpr int kRunFold = 32;         // columns per FP32 run accumulator before the FP64 fold
 
 __device__ __forceinline__ double load_x(const void* x, int32_t dtype, int64_t i) {
@@ -353,6 +354,11 @@ __global__ __launch_bounds__(BLOCK) void k_eval32(EvalArgs a) {
             }
         }
         if (!(fabs(dy * a.s) * (double)(RUN - 1) <= kRunSpan)) ok = false;
+        // the reference relative to the block's first point: within kRunRefMax
+        // scaled units its FP64 rounding (and that of the centred columns near
+        // it) stays below 2^-32 units; a grid tile spans at most about 1100
+        const double u_ref = (y0 - a.y[kb]) * a.s + (double)RUN_REF * dy * a.s;
+        if (!(fabs(u_ref) < kRunRefMax)) ok = false;
     }
     if (!__syncthreads_and(ok)) {
         for (int sub = 0; sub < RUN; ++sub) {

@@ -171,6 +171,9 @@ def test_evenly_spaced_runs_and_their_fallbacks(kp, ctxs):
         # check and its block falls back; other blocks keep the run path
         "piecewise": np.concatenate([np.linspace(lo, 0.0, 4096 + 9, endpoint=False), np.linspace(0.0, hi, 7000)]),
         "perturbed point": np.linspace(lo, hi, 9000) + np.where(np.arange(9000) == 4100, 1e-7, 0.0),
+        # evenly spaced runs far apart within one tile: the second half of the
+        # tile lies 1e7 bandwidths away, beyond the run path's reference range
+        "runs far apart": np.concatenate([np.linspace(-0.5, 0.5, 2048), 1e5 + np.linspace(-0.5, 0.5, 2048)]),
     }
     for name, y in cases.items():
         ref = oracle.kde_eval(x, h, y)
