@@ -205,3 +205,18 @@ def test_runs_are_deterministic_and_flag_nonfinite_points(kp, ctxs):
     with pytest.raises(kp.KdeError) as e:
         c.eval(x, bad, 0.07)
     assert e.value.code == kp.KDE_ENONFINITE
+
+
+@pytest.mark.parametrize("span", [3.99, 4.01])
+@pytest.mark.parametrize("offset", [0.0, 1e6])
+def test_runs_at_the_span_limit_and_far_from_zero(kp, ctxs, span, offset):
+    # grids whose 16-point runs span just under (run path) and just over
+    # (per-point path) 4 scaled units, on data near zero and near 1e6: both
+    # paths within the FP32 bound of the oracle
+    h = 0.2
+    s = math.sqrt(0.5 * math.log2(math.e)) / h
+    x = offset + synth.draw("t3", 20000, 41) * 0.5
+    dy = span / 15.0 / s
+    y = offset + np.arange(-3000, 3000) * dy
+    ref = oracle.kde_eval(x, h, y)
+    assert _rel(ctxs[kp.KDE_FP32_COMP].eval(x, y, h), ref) <= FP32_TOL
