@@ -58,6 +58,20 @@ def test_noalloc_equals_the_allocating_call(kp, prec, pinned):
                 assert abs(got.h - ref.h) <= 1e-12 * ref.h, (n, got.h, ref.h)
 
 
+@pytest.mark.parametrize("R", [2, 4])
+def test_noalloc_with_other_tile_shapes(kp, R):
+    # contexts with 2 or 4 rows per lane: the device-built work list follows
+    # the context's geometry like the host-built one
+    import torch
+    with kp.Context(kp.KDE_FP32_COMP, rows_per_lane=R, target_items=300) as ctx:
+        for n, seed in ((50001, 11), (777, 12)):
+            xd = torch.from_numpy(synth.draw("bimodal", n, seed)).cuda()
+            got = _noalloc(kp, ctx, xd, False)
+            want = ctx.plugin_bandwidth(xd)
+            for k in FIELDS:
+                assert getattr(got, k) == getattr(want, k), (R, n, k)
+
+
 def test_noalloc_float32_input_and_device_status(kp):
     import torch
     with kp.Context(kp.KDE_FP32_COMP) as ctx:
