@@ -116,7 +116,11 @@ typedef struct {
     int32_t rows_per_lane;   /* 0 = from the tune table / default; else 1, 2 or 4          */
     int32_t blocks_per_cu;   /* 0 = from the tune table / occupancy; else 1..16            */
     int32_t target_items;    /* 0 = default; pair work items per stage for large n         */
-    int32_t reserved;
+    int32_t wait_limit_us;   /* 0 = default; else the longest an in-kernel wait for an
+                                earlier stage may take, in microseconds, before the sample
+                                fails with KDE_ETIMEOUT.  The default is 20 s plus the time
+                                of the launch's largest work item at a rate far below any
+                                measured one (so huge samples are never cut off)           */
     int64_t pair_budget;     /* 0 = default; else pair items of about this many pairs for
                                 every n (overrides target_items and the tune table)         */
 } kde_options;

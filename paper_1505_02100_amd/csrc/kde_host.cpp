@@ -383,7 +383,9 @@ LaunchArgs args_for(const kde_ctx* c, Plan& p) {
     a.pubs = (Pub*)p.d_pubs.p;
     a.ticket = (uint32_t*)p.d_ticket.p;
     a.pc = c->pc;
-    a.timeout_ticks = kTimeoutTicks;
+    int64_t wmax = 0;
+    for (const Desc& d : p.descs) wmax = std::max<int64_t>(wmax, d.W);
+    a.timeout_ticks = wait_ticks(c, (int64_t)kBlock * c->R * (wmax + 4));
     return a;
 }
 
@@ -654,7 +656,8 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     if (o.rows_per_lane != 0 && o.rows_per_lane != 1 && o.rows_per_lane != 2 && o.rows_per_lane != 4)
         return set_err(KDE_EINVAL, "rows_per_lane must be 0, 1, 2 or 4");
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 16) return set_err(KDE_EINVAL, "blocks_per_cu out of range");
-    if (o.mem_budget < 0 || o.target_items < 0 || o.pair_budget < 0) return set_err(KDE_EINVAL, "negative option");
+    if (o.mem_budget < 0 || o.target_items < 0 || o.pair_budget < 0 || o.wait_limit_us < 0)
+        return set_err(KDE_EINVAL, "negative option");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev == 0) return set_err(KDE_EDEVICE, "no HIP device available");
@@ -675,6 +678,7 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     c->mem_budget = o.mem_budget;
     c->R = o.rows_per_lane ? o.rows_per_lane : (tt.R ? tt.R : 1);
     c->target_items = o.target_items;
+    c->wait_limit_ticks = (uint64_t)o.wait_limit_us * 100u;  // 100 MHz wall clock
     c->pc = make_consts();
     DeviceGuard dg(c->device);
     hipDeviceProp_t prop;

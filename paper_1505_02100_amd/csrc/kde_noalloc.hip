@@ -236,7 +236,7 @@ extern "C" int kde_plugin_bandwidth_noalloc(kde_ctx* c, const void* x, int64_t n
     a.pubs = p.pubs;
     a.ticket = p.ticket;
     a.pc = c->pc;
-    a.timeout_ticks = kTimeoutTicks;
+    a.timeout_ticks = wait_ticks(c, g.TI * (g.W + 4));
     HIPCHK(launch_persistent(c->precision, c->R, grid_for(c, widest), s, a));
     HIPCHK(launch_results(p.state, p.outmap, 1, dout, s));
     return ok();

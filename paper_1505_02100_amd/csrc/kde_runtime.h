@@ -40,6 +40,12 @@ int hip_fail(hipError_t e, const char* what);
 constexpr int kBlock = 256;             // threads per block of the persistent kernel
 constexpr int64_t kMomentChunk = 2048;  // elements per moment item (8 per thread)
 constexpr uint64_t kTimeoutTicks = 20ull * 100000000ull;  // 20 s at the 100 MHz wall clock
+// A wait for an earlier stage's flag lasts at most as long as that stage's
+// slowest item still in flight (plus its finaliser), so the bound adds the
+// time of the launch's largest pair item at kSlowPairsPerS, a per-block rate
+// far below any measured one: huge samples, whose items take seconds, are
+// not cut off, and a hang still ends.
+constexpr double kSlowPairsPerS = 2e7;
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -144,10 +150,18 @@ struct kde_ctx {
     kde::rt::DevBuf x_stage;                  // host samples copied here
     kde::rt::DevBuf ev_y, ev_out, ev_part, ev_flag;  // density evaluation buffers
     int64_t eval32_resident = 0;              // FP32 evaluation blocks the device holds at once (0: not yet asked)
+    uint64_t wait_limit_ticks = 0;            // kde_options.wait_limit_us in wall-clock ticks; 0 = by item size
 };
 
 namespace kde {
 namespace rt {
+// The wall-clock bound of an in-kernel wait for a launch whose largest pair
+// item has max_item_pairs pairs: the context's own limit, else kTimeoutTicks
+// plus that item's time at kSlowPairsPerS.
+inline uint64_t wait_ticks(const kde_ctx* c, int64_t max_item_pairs) {
+    if (c->wait_limit_ticks) return c->wait_limit_ticks;
+    return kTimeoutTicks + (uint64_t)((double)max_item_pairs / kSlowPairsPerS * 1e8);
+}
 PairGeom pair_geom(const kde_ctx* c, int64_t n);
 int grid_for(const kde_ctx* c, int64_t work);
 // Items of one sample, stage by stage, appended to `out` (slot numbers from

@@ -414,7 +414,10 @@ int launch_step(kde_server* s) {
     a.pubs = (Pub*)s->d_pubs.p;
     a.ticket = ticket;
     a.pc = s->ctx->pc;
-    a.timeout_ticks = kTimeoutTicks;
+    int64_t widest_item = 0;
+    for (size_t k = 0; k < m; ++k)
+        if (listed[k]) widest_item = std::max(widest_item, s->active[k]->geom.TI * (s->active[k]->geom.W + 4));
+    a.timeout_ticks = wait_ticks(s->ctx, widest_item);
     if (launch_persistent(s->ctx->precision, s->ctx->R, step_grid(s->ctx, (int64_t)total), s->stream, a) !=
         hipSuccess) {
         (void)hipGetLastError();

@@ -68,7 +68,7 @@ class kde_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mem_budget", ctypes.c_int64), ("tune_table", ctypes.c_char_p),
                 ("rows_per_lane", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("target_items", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("target_items", ctypes.c_int32), ("wait_limit_us", ctypes.c_int32),
                 ("pair_budget", ctypes.c_int64)]
 
 
@@ -274,7 +274,7 @@ def kde_options_init() -> kde_options:
 
 def kde_ctx_create(precision: int = KDE_FP64_PLAIN, device: int = 0, mem_budget: int = 0,
                    rows_per_lane: int = 0, blocks_per_cu: int = 0, target_items: int = 0,
-                   tune_table: Optional[str] = None, pair_budget: int = 0) -> int:
+                   tune_table: Optional[str] = None, pair_budget: int = 0, wait_limit_us: int = 0) -> int:
     o = kde_options_init()
     o.device = device
     o.precision = precision
@@ -283,6 +283,7 @@ def kde_ctx_create(precision: int = KDE_FP64_PLAIN, device: int = 0, mem_budget:
     o.blocks_per_cu = blocks_per_cu
     o.target_items = target_items
     o.pair_budget = pair_budget
+    o.wait_limit_us = wait_limit_us
     o.tune_table = tune_table.encode() if tune_table else None
     h = _P()
     _check(_lib.kde_ctx_create(ctypes.byref(h), ctypes.byref(o)), "kde_ctx_create")

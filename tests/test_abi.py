@@ -53,6 +53,13 @@ def test_host_only_entry_points():
     res = kp.kde_result()
     assert kp._lib.kde_plugin_bandwidth_ex(None, None, 5, 0, 0, None, ctypes.byref(res)) == kp.KDE_EINVAL
     assert kp._lib.kde_eval_ex(None, None, 5, 0, 0, None, 3, 0, 0.5, None, None) == kp.KDE_EINVAL
+    # negative options are refused before the device is touched
+    for field in ("wait_limit_us", "target_items", "pair_budget", "mem_budget"):
+        o = kp.kde_options_init()
+        setattr(o, field, -1)
+        h = kp._P()
+        assert kp._lib.kde_ctx_create(ctypes.byref(h), ctypes.byref(o)) == kp.KDE_EINVAL, field
+        assert not h.value
 
 
 def test_binding_names_match_the_header():

@@ -1,9 +1,11 @@
 """The host runtime around the kernels, through the C ABI: the context's
 device-memory budget and its plan cache (eviction and reuse), contexts used
 from several host threads at once (one context per thread, and the literal
-calls' shared default context), and thread-local error state.  Results must
-be bitwise those of the same calls made one at a time."""
+calls' shared default context), thread-local error state, and the bound on
+in-kernel waits.  Results must be bitwise those of the same calls made one at
+a time."""
 import ctypes
+import math
 import threading
 
 import numpy as np
@@ -127,3 +129,27 @@ def test_errors_are_per_thread(kp):
     tb.join(60)
     assert seen["bad"] == kp.KDE_EINVAL
     assert seen["good"] == (kp.KDE_OK, kp.KDE_OK)
+
+
+def test_wait_limit_fails_the_sample_and_the_launch_ends(kp):
+    # a 1 us limit on the in-kernel waits for an earlier stage, forced from the
+    # host: at n = 2^18 the first blocks to run out of Step IV items wait tens
+    # of microseconds for the stage's last items, so the selection fails with
+    # KDE_ETIMEOUT (h NaN) while every block still leaves the kernel; a limit
+    # of 10 s, and the default limit, give the normal result bitwise
+    import torch
+    x = torch.from_numpy(synth.bimodal(1 << 18, 21)).cuda()
+    with kp.Context(kp.KDE_FP32_COMP, wait_limit_us=1) as c:
+        for _ in range(2):
+            r = c.plugin_bandwidth(x, check=False)
+            assert r.status == kp.KDE_ETIMEOUT and math.isnan(r.h)
+        with pytest.raises(kp.KdeError) as e:
+            c.plugin_bandwidth(x)
+        assert e.value.code == kp.KDE_ETIMEOUT
+        out = c.plugin_bandwidth_batch([x, x[:5000].contiguous()])
+        assert out[0].status == kp.KDE_ETIMEOUT
+    with kp.Context(kp.KDE_FP32_COMP) as c:
+        want = c.plugin_bandwidth(x)
+    with kp.Context(kp.KDE_FP32_COMP, wait_limit_us=10_000_000) as c:
+        got = c.plugin_bandwidth(x)
+    assert want.status == 0 and (got.h, got.psi6, got.psi4) == (want.h, want.psi6, want.psi4)
