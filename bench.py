@@ -461,6 +461,7 @@ def main():
     value = pairs / ((t1 - t0) / args.steps)
     timeline = ctx.last_timeline(0)
     cfg = ctx.config()
+    cfg["launch"] = ctx.last_launch()   # blocks and waves per SIMD of the timed kernel
     dev_ms_avg = float(np.mean(dev_ms))
 
     achieved = flop / (dev_ms_avg * 1e-3) / 1e12

@@ -166,6 +166,13 @@ KDE_API int kde_ctx_config(const kde_ctx* ctx, int32_t* rows_per_lane, int32_t* 
  * it), measured with HIP events on the caller's stream; -1 if none yet. */
 KDE_API double kde_ctx_last_device_ms(const kde_ctx* ctx);
 
+/* Launch shape of the last synchronous call's persistent kernel on this
+ * context: its blocks (256 threads each) and the waves per SIMD the kernel is
+ * built for (3, or 4 for the default precision at R = 1 on samples of
+ * 2^18 elements or more when the context chose its own tile configuration).
+ * KDE_EINVAL if the context has made no synchronous call yet. */
+KDE_API int kde_ctx_last_launch(const kde_ctx* ctx, int32_t* blocks, int32_t* waves_per_simd);
+
 /* Device timeline of sample `sample` of the last synchronous call on this
  * context: ms[k] (k < KDE_NUM_STAGES; the caller provides that many) =
  * milliseconds from the start of the sample's first work item to the moment

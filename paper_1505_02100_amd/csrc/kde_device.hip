@@ -379,137 +379,137 @@ __device__ __forceinline__ void pair16_loop_r4_f32(uint32_t addr, int32_t cnt, f
         "s_nop 0\n"
         "s_nop 0\n"
         "1:\n"
-        "v_mov_b32_e32 v85, %[addr]\n"
-        "ds_read_b128 v[80:83], v85 offset:16\n"
-        "ds_read_b128 v[86:89], v85 offset:48\n"
-        "ds_read_b128 v[90:93], v85\n"
-        "ds_read_b128 v[94:97], v85 offset:32\n"
+        "v_mov_b32_e32 v45, %[addr]\n"
+        "ds_read_b128 v[40:43], v45 offset:16\n"
+        "ds_read_b128 v[46:49], v45 offset:48\n"
+        "ds_read_b128 v[50:53], v45\n"
+        "ds_read_b128 v[54:57], v45 offset:32\n"
         "s_add_u32 %[addr], %[addr], 64\n"
         "s_sub_u32 %[cnt], %[cnt], 1\n"
         "s_waitcnt lgkmcnt(0)\n"
-        "v_sub_f32_e32 v82, %[ui], v82\n"
-        "v_sub_f32_e32 v96, %[ui], v96\n"
-        "v_sub_f32_e32 v86, %[ui], v86\n"
-        "v_sub_f32_e32 v91, %[ui], v91\n"
-        "v_fmaak_f32 v99, v86, v86, 0xc0c00000\n"
-        "v_sub_f32_e32 v81, %[ui], v81\n"
-        "v_sub_f32_e32 v89, %[ui], v89\n"
-        "v_fmaak_f32 v100, v81, v81, 0xc0c00000\n"
-        "v_sub_f32_e32 v83, %[ui], v83\n"
-        "v_sub_f32_e32 v97, %[ui], v97\n"
-        "v_mul_f32_e32 v81, v81, v81\n"
-        "v_fmaak_f32 v101, v83, v83, 0xc0c00000\n"
-        "v_mul_f32_e32 v125, v97, v97\n"
-        "v_fmaak_f32 v132, v91, v91, 0xc0c00000\n"
-        "v_mul_f32_e32 v83, v83, v83\n"
-        "v_mul_f32_e32 v133, v82, v82\n"
-        "v_fmaak_f32 v100, v100, v81, 0x40400000\n"
-        "v_sub_f32_e32 v92, %[ui], v92\n"
-        "v_sub_f32_e32 v87, %[ui], v87\n"
-        "v_mul_f32_e32 v134, v89, v89\n"
-        "v_fmaak_f32 v135, v96, v96, 0xc0c00000\n"
-        "v_mul_f32_e64 v81, v81, -%[k]\n"
-        "v_sub_f32_e32 v88, %[ui], v88\n"
-        "v_mul_f32_e32 v96, v96, v96\n"
-        "v_fmaak_f32 v101, v101, v83, 0x40400000\n"
-        "v_mul_f32_e32 v136, v87, v87\n"
-        "v_mul_f32_e32 v137, v88, v88\n"
-        "v_fmaak_f32 v138, v92, v92, 0xc0c00000\n"
-        "v_mul_f32_e32 v91, v91, v91\n"
-        "v_sub_f32_e32 v94, %[ui], v94\n"
-        "v_fmaak_f32 v139, v94, v94, 0xc0c00000\n"
-        "v_sub_f32_e32 v80, %[ui], v80\n"
-        "v_sub_f32_e32 v93, %[ui], v93\n"
-        "v_mul_f32_e32 v140, v93, v93\n"
-        "v_fmaak_f32 v97, v97, v97, 0xc0c00000\n"
-        "v_fmaak_f32 v88, v88, v88, 0xc0c00000\n"
-        "v_fmaak_f32 v135, v135, v96, 0x40400000\n"
-        "v_mul_f32_e32 v86, v86, v86\n"
-        "v_fmaak_f32 v141, v80, v80, 0xc0c00000\n"
-        "v_fmaak_f32 v87, v87, v87, 0xc0c00000\n"
-        "v_mul_f32_e32 v80, v80, v80\n"
-        "v_mul_f32_e32 v94, v94, v94\n"
-        "v_fmaak_f32 v89, v89, v89, 0xc0c00000\n"
-        "v_fmaak_f32 v139, v139, v94, 0x40400000\n"
-        "v_fmaak_f32 v93, v93, v93, 0xc0c00000\n"
-        "v_sub_f32_e32 v95, %[ui], v95\n"
-        "v_fmaak_f32 v132, v132, v91, 0x40400000\n"
-        "v_fmaak_f32 v142, v95, v95, 0xc0c00000\n"
-        "v_fmaak_f32 v89, v89, v134, 0x40400000\n"
-        "v_fmaak_f32 v97, v97, v125, 0x40400000\n"
-        "v_sub_f32_e32 v90, %[ui], v90\n"
-        "v_fmaak_f32 v99, v99, v86, 0x40400000\n"
-        "v_fmaak_f32 v93, v93, v140, 0x40400000\n"
-        "v_fmaak_f32 v143, v90, v90, 0xc0c00000\n"
-        "v_fmaak_f32 v141, v141, v80, 0x40400000\n"
-        "v_mul_f32_e32 v90, v90, v90\n"
-        "v_fmaak_f32 v82, v82, v82, 0xc0c00000\n"
-        "v_fmaak_f32 v88, v88, v137, 0x40400000\n"
-        "v_fmaak_f32 v82, v82, v133, 0x40400000\n"
-        "v_fmaak_f32 v143, v143, v90, 0x40400000\n"
-        "v_mul_f32_e32 v95, v95, v95\n"
-        "v_mul_f32_e64 v86, v86, -%[k]\n"
-        "v_mul_f32_e64 v140, v140, -%[k]\n"
-        "v_mul_f32_e64 v90, v90, -%[k]\n"
-        "v_mul_f32_e64 v125, v125, -%[k]\n"
-        "v_mul_f32_e64 v133, v133, -%[k]\n"
-        "v_mul_f32_e64 v83, v83, -%[k]\n"
-        "v_mul_f32_e64 v91, v91, -%[k]\n"
+        "v_sub_f32_e32 v42, %[ui], v42\n"
+        "v_sub_f32_e32 v56, %[ui], v56\n"
+        "v_sub_f32_e32 v46, %[ui], v46\n"
+        "v_sub_f32_e32 v51, %[ui], v51\n"
+        "v_fmaak_f32 v59, v46, v46, 0xc0c00000\n"
+        "v_sub_f32_e32 v41, %[ui], v41\n"
+        "v_sub_f32_e32 v49, %[ui], v49\n"
+        "v_fmaak_f32 v60, v41, v41, 0xc0c00000\n"
+        "v_sub_f32_e32 v43, %[ui], v43\n"
+        "v_sub_f32_e32 v57, %[ui], v57\n"
+        "v_mul_f32_e32 v41, v41, v41\n"
+        "v_fmaak_f32 v61, v43, v43, 0xc0c00000\n"
+        "v_mul_f32_e32 v85, v57, v57\n"
+        "v_fmaak_f32 v92, v51, v51, 0xc0c00000\n"
+        "v_mul_f32_e32 v43, v43, v43\n"
+        "v_mul_f32_e32 v93, v42, v42\n"
+        "v_fmaak_f32 v60, v60, v41, 0x40400000\n"
+        "v_sub_f32_e32 v52, %[ui], v52\n"
+        "v_sub_f32_e32 v47, %[ui], v47\n"
+        "v_mul_f32_e32 v94, v49, v49\n"
+        "v_fmaak_f32 v95, v56, v56, 0xc0c00000\n"
+        "v_mul_f32_e64 v41, v41, -%[k]\n"
+        "v_sub_f32_e32 v48, %[ui], v48\n"
+        "v_mul_f32_e32 v56, v56, v56\n"
+        "v_fmaak_f32 v61, v61, v43, 0x40400000\n"
+        "v_mul_f32_e32 v96, v47, v47\n"
+        "v_mul_f32_e32 v97, v48, v48\n"
+        "v_fmaak_f32 v98, v52, v52, 0xc0c00000\n"
+        "v_mul_f32_e32 v51, v51, v51\n"
+        "v_sub_f32_e32 v54, %[ui], v54\n"
+        "v_fmaak_f32 v99, v54, v54, 0xc0c00000\n"
+        "v_sub_f32_e32 v40, %[ui], v40\n"
+        "v_sub_f32_e32 v53, %[ui], v53\n"
+        "v_mul_f32_e32 v100, v53, v53\n"
+        "v_fmaak_f32 v57, v57, v57, 0xc0c00000\n"
+        "v_fmaak_f32 v48, v48, v48, 0xc0c00000\n"
+        "v_fmaak_f32 v95, v95, v56, 0x40400000\n"
+        "v_mul_f32_e32 v46, v46, v46\n"
+        "v_fmaak_f32 v101, v40, v40, 0xc0c00000\n"
+        "v_fmaak_f32 v47, v47, v47, 0xc0c00000\n"
+        "v_mul_f32_e32 v40, v40, v40\n"
+        "v_mul_f32_e32 v54, v54, v54\n"
+        "v_fmaak_f32 v49, v49, v49, 0xc0c00000\n"
+        "v_fmaak_f32 v99, v99, v54, 0x40400000\n"
+        "v_fmaak_f32 v53, v53, v53, 0xc0c00000\n"
+        "v_sub_f32_e32 v55, %[ui], v55\n"
+        "v_fmaak_f32 v92, v92, v51, 0x40400000\n"
+        "v_fmaak_f32 v102, v55, v55, 0xc0c00000\n"
+        "v_fmaak_f32 v49, v49, v94, 0x40400000\n"
+        "v_fmaak_f32 v57, v57, v85, 0x40400000\n"
+        "v_sub_f32_e32 v50, %[ui], v50\n"
+        "v_fmaak_f32 v59, v59, v46, 0x40400000\n"
+        "v_fmaak_f32 v53, v53, v100, 0x40400000\n"
+        "v_fmaak_f32 v103, v50, v50, 0xc0c00000\n"
+        "v_fmaak_f32 v101, v101, v40, 0x40400000\n"
+        "v_mul_f32_e32 v50, v50, v50\n"
+        "v_fmaak_f32 v42, v42, v42, 0xc0c00000\n"
+        "v_fmaak_f32 v48, v48, v97, 0x40400000\n"
+        "v_fmaak_f32 v42, v42, v93, 0x40400000\n"
+        "v_fmaak_f32 v103, v103, v50, 0x40400000\n"
+        "v_mul_f32_e32 v55, v55, v55\n"
+        "v_mul_f32_e64 v46, v46, -%[k]\n"
+        "v_mul_f32_e64 v100, v100, -%[k]\n"
+        "v_mul_f32_e64 v50, v50, -%[k]\n"
+        "v_mul_f32_e64 v85, v85, -%[k]\n"
+        "v_mul_f32_e64 v93, v93, -%[k]\n"
+        "v_mul_f32_e64 v43, v43, -%[k]\n"
+        "v_mul_f32_e64 v51, v51, -%[k]\n"
+        "v_mul_f32_e64 v54, v54, -%[k]\n"
         "v_mul_f32_e64 v94, v94, -%[k]\n"
-        "v_mul_f32_e64 v134, v134, -%[k]\n"
-        "v_mul_f32_e64 v137, v137, -%[k]\n"
-        "v_mul_f32_e64 v96, v96, -%[k]\n"
-        "v_mul_f32_e64 v80, v80, -%[k]\n"
-        "v_exp_f32_e32 v140, v140\n"
-        "v_exp_f32_e32 v96, v96\n"
-        "v_exp_f32_e32 v86, v86\n"
-        "v_exp_f32_e32 v133, v133\n"
-        "v_exp_f32_e32 v80, v80\n"
-        "v_exp_f32_e32 v90, v90\n"
-        "v_exp_f32_e32 v91, v91\n"
-        "v_exp_f32_e32 v81, v81\n"
-        "v_exp_f32_e32 v83, v83\n"
-        "v_exp_f32_e32 v137, v137\n"
-        "v_exp_f32_e32 v134, v134\n"
-        "v_exp_f32_e32 v125, v125\n"
+        "v_mul_f32_e64 v97, v97, -%[k]\n"
+        "v_mul_f32_e64 v56, v56, -%[k]\n"
+        "v_mul_f32_e64 v40, v40, -%[k]\n"
+        "v_exp_f32_e32 v100, v100\n"
+        "v_exp_f32_e32 v56, v56\n"
+        "v_exp_f32_e32 v46, v46\n"
+        "v_exp_f32_e32 v93, v93\n"
+        "v_exp_f32_e32 v40, v40\n"
+        "v_exp_f32_e32 v50, v50\n"
+        "v_exp_f32_e32 v51, v51\n"
+        "v_exp_f32_e32 v41, v41\n"
+        "v_exp_f32_e32 v43, v43\n"
+        "v_exp_f32_e32 v97, v97\n"
         "v_exp_f32_e32 v94, v94\n"
-        "v_fmaak_f32 v87, v87, v136, 0x40400000\n"
-        "v_fmaak_f32 v142, v142, v95, 0x40400000\n"
-        "v_mul_f32_e32 v93, v93, v140\n"
-        "v_mul_f32_e32 v140, v132, v91\n"
-        "v_mul_f32_e32 v132, v92, v92\n"
-        "v_fmaak_f32 v91, v138, v132, 0x40400000\n"
-        "v_fmac_f32_e32 v93, v101, v83\n"
-        "v_fmac_f32_e32 v93, v97, v125\n"
-        "v_fmac_f32_e32 v140, v100, v81\n"
-        "v_mul_f32_e32 v92, v143, v90\n"
-        "v_fmac_f32_e32 v92, v141, v80\n"
-        "v_fmac_f32_e32 v92, v139, v94\n"
-        "v_fmac_f32_e32 v93, v89, v134\n"
-        "v_fmac_f32_e32 v92, v99, v86\n"
-        "v_mul_f32_e64 v138, v95, -%[k]\n"
-        "v_mul_f32_e64 v101, v132, -%[k]\n"
-        "v_mul_f32_e64 v83, v136, -%[k]\n"
-        "v_exp_f32_e32 v97, v83\n"
-        "v_exp_f32_e32 v125, v138\n"
-        "v_exp_f32_e32 v100, v101\n"
+        "v_exp_f32_e32 v85, v85\n"
+        "v_exp_f32_e32 v54, v54\n"
+        "v_fmaak_f32 v47, v47, v96, 0x40400000\n"
+        "v_fmaak_f32 v102, v102, v55, 0x40400000\n"
+        "v_mul_f32_e32 v53, v53, v100\n"
+        "v_mul_f32_e32 v100, v92, v51\n"
+        "v_mul_f32_e32 v92, v52, v52\n"
+        "v_fmaak_f32 v51, v98, v92, 0x40400000\n"
+        "v_fmac_f32_e32 v53, v61, v43\n"
+        "v_fmac_f32_e32 v53, v57, v85\n"
+        "v_fmac_f32_e32 v100, v60, v41\n"
+        "v_mul_f32_e32 v52, v103, v50\n"
+        "v_fmac_f32_e32 v52, v101, v40\n"
+        "v_fmac_f32_e32 v52, v99, v54\n"
+        "v_fmac_f32_e32 v53, v49, v94\n"
+        "v_fmac_f32_e32 v52, v59, v46\n"
+        "v_mul_f32_e64 v98, v55, -%[k]\n"
+        "v_mul_f32_e64 v61, v92, -%[k]\n"
+        "v_mul_f32_e64 v43, v96, -%[k]\n"
+        "v_exp_f32_e32 v57, v43\n"
+        "v_exp_f32_e32 v85, v98\n"
+        "v_exp_f32_e32 v60, v61\n"
         "s_nop 0\n"
-        "v_mul_f32_e32 v81, v91, v100\n"
-        "v_fmac_f32_e32 v81, v82, v133\n"
-        "v_fmac_f32_e32 v81, v135, v96\n"
-        "v_fmac_f32_e32 v81, v88, v137\n"
-        "v_fmac_f32_e32 v140, v142, v125\n"
-        "v_fmac_f32_e32 v140, v87, v97\n"
-        "v_add_f32_e32 v143, v92, v140\n"
-        "v_add_f32_e32 v90, v81, v93\n"
-        "v_add_f32_e32 v141, v143, v90\n"
-        "v_cvt_f64_f32_e32 v[82:83], v141\n"
+        "v_mul_f32_e32 v41, v51, v60\n"
+        "v_fmac_f32_e32 v41, v42, v93\n"
+        "v_fmac_f32_e32 v41, v95, v56\n"
+        "v_fmac_f32_e32 v41, v48, v97\n"
+        "v_fmac_f32_e32 v100, v102, v85\n"
+        "v_fmac_f32_e32 v100, v47, v57\n"
+        "v_add_f32_e32 v103, v52, v100\n"
+        "v_add_f32_e32 v50, v41, v53\n"
+        "v_add_f32_e32 v101, v103, v50\n"
+        "v_cvt_f64_f32_e32 v[42:43], v101\n"
         "s_cmp_lg_u32 %[cnt], 0\n"
-        "v_add_f64 %[tot], %[tot], v[82:83]\n"
+        "v_add_f64 %[tot], %[tot], v[42:43]\n"
         "s_cbranch_scc1 1b\n"
-        : [tot] "+{v[74:75]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
-        : [ui] "{v84}"(ui), [k] "s"(k)
-        : "v80", "v81", "v82", "v83", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v99", "v100", "v101", "v125", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "scc", "memory");
+        : [tot] "+{v[34:35]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
+        : [ui] "{v44}"(ui), [k] "s"(k)
+        : "v40", "v41", "v42", "v43", "v45", "v46", "v47", "v48", "v49", "v50", "v51", "v52", "v53", "v54", "v55", "v56", "v57", "v59", "v60", "v61", "v85", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101", "v102", "v103", "scc", "memory");
 }
 
 // Step IV at R = 1 without the clamp (the default FP32 path), over cnt >= 1
@@ -533,136 +533,136 @@ __device__ __forceinline__ void pair16_loop_r6_f32(uint32_t addr, int32_t cnt, f
         "s_nop 0\n"
         "s_nop 0\n"
         "1:\n"
-        "v_mov_b32_e32 v85, %[addr]\n"
-        "ds_read_b128 v[80:83], v85\n"
-        "ds_read_b128 v[86:89], v85 offset:16\n"
-        "ds_read_b128 v[90:93], v85 offset:32\n"
-        "ds_read_b128 v[94:97], v85 offset:48\n"
+        "v_mov_b32_e32 v45, %[addr]\n"
+        "ds_read_b128 v[40:43], v45\n"
+        "ds_read_b128 v[46:49], v45 offset:16\n"
+        "ds_read_b128 v[50:53], v45 offset:32\n"
+        "ds_read_b128 v[54:57], v45 offset:48\n"
         "s_add_u32 %[addr], %[addr], 64\n"
         "s_waitcnt lgkmcnt(0)\n"
-        "v_sub_f32_e32 v80, %[ui], v80\n"
-        "v_sub_f32_e32 v81, %[ui], v81\n"
-        "v_sub_f32_e32 v82, %[ui], v82\n"
-        "v_sub_f32_e32 v83, %[ui], v83\n"
-        "v_sub_f32_e32 v85, %[ui], v86\n"
-        "v_sub_f32_e32 v86, %[ui], v87\n"
-        "v_sub_f32_e32 v87, %[ui], v88\n"
-        "v_sub_f32_e32 v88, %[ui], v89\n"
-        "v_fmaak_f32 v80, v80, v80, 0xc0a00000\n"
-        "v_fmaak_f32 v81, v81, v81, 0xc0a00000\n"
-        "v_fmaak_f32 v82, v82, v82, 0xc0a00000\n"
-        "v_fmaak_f32 v83, v83, v83, 0xc0a00000\n"
-        "v_sub_f32_e32 v89, %[ui], v90\n"
-        "v_sub_f32_e32 v90, %[ui], v91\n"
-        "v_sub_f32_e32 v91, %[ui], v92\n"
-        "v_sub_f32_e32 v92, %[ui], v93\n"
-        "v_sub_f32_e32 v93, %[ui], v94\n"
-        "v_sub_f32_e32 v94, %[ui], v95\n"
-        "v_sub_f32_e32 v95, %[ui], v96\n"
-        "v_sub_f32_e32 v96, %[ui], v97\n"
-        "v_fmaak_f32 v85, v85, v85, 0xc0a00000\n"
-        "v_fmaak_f32 v86, v86, v86, 0xc0a00000\n"
-        "v_fmaak_f32 v87, v87, v87, 0xc0a00000\n"
-        "v_fmaak_f32 v88, v88, v88, 0xc0a00000\n"
-        "v_fmaak_f32 v97, v80, v80, 0xc1f00000\n"
-        "v_fmaak_f32 v98, v81, v81, 0xc1f00000\n"
-        "v_fmaak_f32 v99, v82, v82, 0xc1f00000\n"
-        "v_fmaak_f32 v100, v83, v83, 0xc1f00000\n"
-        "v_mul_f32_e64 v101, v80, -%[k]\n"
-        "v_mul_f32_e64 v125, v81, -%[k]\n"
-        "v_mul_f32_e64 v132, v82, -%[k]\n"
-        "v_mul_f32_e64 v133, v83, -%[k]\n"
-        "v_fmaak_f32 v89, v89, v89, 0xc0a00000\n"
-        "v_fmaak_f32 v90, v90, v90, 0xc0a00000\n"
-        "v_fmaak_f32 v91, v91, v91, 0xc0a00000\n"
-        "v_fmaak_f32 v92, v92, v92, 0xc0a00000\n"
-        "v_mul_f32_e64 v138, v85, -%[k]\n"
-        "v_mul_f32_e64 v139, v86, -%[k]\n"
-        "v_mul_f32_e64 v140, v87, -%[k]\n"
-        "v_mul_f32_e64 v141, v88, -%[k]\n"
-        "v_fmaak_f32 v80, v97, v80, 0xc2200000\n"
-        "v_fmaak_f32 v81, v98, v81, 0xc2200000\n"
-        "v_fmaak_f32 v82, v99, v82, 0xc2200000\n"
-        "v_fmaak_f32 v83, v100, v83, 0xc2200000\n"
-        "v_exp_f32_e32 v97, v101\n"
-        "v_exp_f32_e32 v98, v125\n"
-        "v_exp_f32_e32 v99, v132\n"
-        "v_exp_f32_e32 v100, v133\n"
-        "v_fmaak_f32 v93, v93, v93, 0xc0a00000\n"
-        "v_fmaak_f32 v94, v94, v94, 0xc0a00000\n"
-        "v_fmaak_f32 v95, v95, v95, 0xc0a00000\n"
-        "v_fmaak_f32 v96, v96, v96, 0xc0a00000\n"
-        "v_fmaak_f32 v134, v85, v85, 0xc1f00000\n"
-        "v_fmaak_f32 v135, v86, v86, 0xc1f00000\n"
-        "v_fmaak_f32 v136, v87, v87, 0xc1f00000\n"
-        "v_fmaak_f32 v137, v88, v88, 0xc1f00000\n"
-        "v_mul_f32_e64 v146, v89, -%[k]\n"
-        "v_mul_f32_e64 v147, v90, -%[k]\n"
-        "v_mul_f32_e64 v148, v91, -%[k]\n"
-        "v_mul_f32_e64 v149, v92, -%[k]\n"
-        "v_exp_f32_e32 v101, v138\n"
-        "v_exp_f32_e32 v125, v139\n"
-        "v_exp_f32_e32 v132, v140\n"
-        "v_exp_f32_e32 v133, v141\n"
-        "v_mul_f32_e64 v154, v93, -%[k]\n"
-        "v_mul_f32_e64 v155, v94, -%[k]\n"
-        "v_mul_f32_e64 v156, v95, -%[k]\n"
-        "v_mul_f32_e64 v157, v96, -%[k]\n"
-        "v_fmaak_f32 v85, v134, v85, 0xc2200000\n"
-        "v_fmaak_f32 v86, v135, v86, 0xc2200000\n"
-        "v_fmaak_f32 v87, v136, v87, 0xc2200000\n"
-        "v_fmaak_f32 v88, v137, v88, 0xc2200000\n"
-        "v_exp_f32_e32 v134, v146\n"
-        "v_exp_f32_e32 v135, v147\n"
-        "v_exp_f32_e32 v136, v148\n"
-        "v_exp_f32_e32 v137, v149\n"
-        "v_exp_f32_e32 v138, v154\n"
-        "v_exp_f32_e32 v139, v155\n"
-        "v_exp_f32_e32 v140, v156\n"
-        "v_exp_f32_e32 v141, v157\n"
-        "v_fmaak_f32 v142, v89, v89, 0xc1f00000\n"
-        "v_fmaak_f32 v143, v90, v90, 0xc1f00000\n"
-        "v_fmaak_f32 v144, v91, v91, 0xc1f00000\n"
-        "v_fmaak_f32 v145, v92, v92, 0xc1f00000\n"
-        "v_fma_f32 v80, v80, v97, 0\n"
-        "v_fma_f32 v81, v81, v98, 0\n"
-        "v_fma_f32 v82, v82, v99, 0\n"
-        "v_fma_f32 v83, v83, v100, 0\n"
-        "v_fmaak_f32 v150, v93, v93, 0xc1f00000\n"
-        "v_fmaak_f32 v151, v94, v94, 0xc1f00000\n"
-        "v_fmaak_f32 v152, v95, v95, 0xc1f00000\n"
-        "v_fmaak_f32 v153, v96, v96, 0xc1f00000\n"
-        "v_fmaak_f32 v89, v142, v89, 0xc2200000\n"
-        "v_fmaak_f32 v90, v143, v90, 0xc2200000\n"
-        "v_fmaak_f32 v91, v144, v91, 0xc2200000\n"
-        "v_fmaak_f32 v92, v145, v92, 0xc2200000\n"
-        "v_fmac_f32_e32 v80, v85, v101\n"
-        "v_fmac_f32_e32 v81, v86, v125\n"
-        "v_fmac_f32_e32 v82, v87, v132\n"
-        "v_fmac_f32_e32 v83, v88, v133\n"
-        "v_fmaak_f32 v93, v150, v93, 0xc2200000\n"
-        "v_fmaak_f32 v94, v151, v94, 0xc2200000\n"
-        "v_fmaak_f32 v95, v152, v95, 0xc2200000\n"
-        "v_fmaak_f32 v96, v153, v96, 0xc2200000\n"
-        "v_fmac_f32_e32 v80, v89, v134\n"
-        "v_fmac_f32_e32 v81, v90, v135\n"
-        "v_fmac_f32_e32 v82, v91, v136\n"
-        "v_fmac_f32_e32 v83, v92, v137\n"
-        "v_fmac_f32_e32 v80, v93, v138\n"
-        "v_fmac_f32_e32 v81, v94, v139\n"
-        "v_fmac_f32_e32 v82, v95, v140\n"
-        "v_fmac_f32_e32 v83, v96, v141\n"
-        "v_add_f32_e32 v80, v80, v81\n"
-        "v_add_f32_e32 v81, v82, v83\n"
+        "v_sub_f32_e32 v40, %[ui], v40\n"
+        "v_sub_f32_e32 v41, %[ui], v41\n"
+        "v_sub_f32_e32 v42, %[ui], v42\n"
+        "v_sub_f32_e32 v43, %[ui], v43\n"
+        "v_sub_f32_e32 v45, %[ui], v46\n"
+        "v_sub_f32_e32 v46, %[ui], v47\n"
+        "v_sub_f32_e32 v47, %[ui], v48\n"
+        "v_sub_f32_e32 v48, %[ui], v49\n"
+        "v_fmaak_f32 v40, v40, v40, 0xc0a00000\n"
+        "v_fmaak_f32 v41, v41, v41, 0xc0a00000\n"
+        "v_fmaak_f32 v42, v42, v42, 0xc0a00000\n"
+        "v_fmaak_f32 v43, v43, v43, 0xc0a00000\n"
+        "v_sub_f32_e32 v49, %[ui], v50\n"
+        "v_sub_f32_e32 v50, %[ui], v51\n"
+        "v_sub_f32_e32 v51, %[ui], v52\n"
+        "v_sub_f32_e32 v52, %[ui], v53\n"
+        "v_sub_f32_e32 v53, %[ui], v54\n"
+        "v_sub_f32_e32 v54, %[ui], v55\n"
+        "v_sub_f32_e32 v55, %[ui], v56\n"
+        "v_sub_f32_e32 v56, %[ui], v57\n"
+        "v_fmaak_f32 v45, v45, v45, 0xc0a00000\n"
+        "v_fmaak_f32 v46, v46, v46, 0xc0a00000\n"
+        "v_fmaak_f32 v47, v47, v47, 0xc0a00000\n"
+        "v_fmaak_f32 v48, v48, v48, 0xc0a00000\n"
+        "v_fmaak_f32 v57, v40, v40, 0xc1f00000\n"
+        "v_fmaak_f32 v58, v41, v41, 0xc1f00000\n"
+        "v_fmaak_f32 v59, v42, v42, 0xc1f00000\n"
+        "v_fmaak_f32 v60, v43, v43, 0xc1f00000\n"
+        "v_mul_f32_e64 v61, v40, -%[k]\n"
+        "v_mul_f32_e64 v85, v41, -%[k]\n"
+        "v_mul_f32_e64 v92, v42, -%[k]\n"
+        "v_mul_f32_e64 v93, v43, -%[k]\n"
+        "v_fmaak_f32 v49, v49, v49, 0xc0a00000\n"
+        "v_fmaak_f32 v50, v50, v50, 0xc0a00000\n"
+        "v_fmaak_f32 v51, v51, v51, 0xc0a00000\n"
+        "v_fmaak_f32 v52, v52, v52, 0xc0a00000\n"
+        "v_mul_f32_e64 v98, v45, -%[k]\n"
+        "v_mul_f32_e64 v99, v46, -%[k]\n"
+        "v_mul_f32_e64 v100, v47, -%[k]\n"
+        "v_mul_f32_e64 v101, v48, -%[k]\n"
+        "v_fmaak_f32 v40, v57, v40, 0xc2200000\n"
+        "v_fmaak_f32 v41, v58, v41, 0xc2200000\n"
+        "v_fmaak_f32 v42, v59, v42, 0xc2200000\n"
+        "v_fmaak_f32 v43, v60, v43, 0xc2200000\n"
+        "v_exp_f32_e32 v57, v61\n"
+        "v_exp_f32_e32 v58, v85\n"
+        "v_exp_f32_e32 v59, v92\n"
+        "v_exp_f32_e32 v60, v93\n"
+        "v_fmaak_f32 v53, v53, v53, 0xc0a00000\n"
+        "v_fmaak_f32 v54, v54, v54, 0xc0a00000\n"
+        "v_fmaak_f32 v55, v55, v55, 0xc0a00000\n"
+        "v_fmaak_f32 v56, v56, v56, 0xc0a00000\n"
+        "v_fmaak_f32 v94, v45, v45, 0xc1f00000\n"
+        "v_fmaak_f32 v95, v46, v46, 0xc1f00000\n"
+        "v_fmaak_f32 v96, v47, v47, 0xc1f00000\n"
+        "v_fmaak_f32 v97, v48, v48, 0xc1f00000\n"
+        "v_mul_f32_e64 v106, v49, -%[k]\n"
+        "v_mul_f32_e64 v107, v50, -%[k]\n"
+        "v_mul_f32_e64 v108, v51, -%[k]\n"
+        "v_mul_f32_e64 v109, v52, -%[k]\n"
+        "v_exp_f32_e32 v61, v98\n"
+        "v_exp_f32_e32 v85, v99\n"
+        "v_exp_f32_e32 v92, v100\n"
+        "v_exp_f32_e32 v93, v101\n"
+        "v_mul_f32_e64 v114, v53, -%[k]\n"
+        "v_mul_f32_e64 v115, v54, -%[k]\n"
+        "v_mul_f32_e64 v116, v55, -%[k]\n"
+        "v_mul_f32_e64 v117, v56, -%[k]\n"
+        "v_fmaak_f32 v45, v94, v45, 0xc2200000\n"
+        "v_fmaak_f32 v46, v95, v46, 0xc2200000\n"
+        "v_fmaak_f32 v47, v96, v47, 0xc2200000\n"
+        "v_fmaak_f32 v48, v97, v48, 0xc2200000\n"
+        "v_exp_f32_e32 v94, v106\n"
+        "v_exp_f32_e32 v95, v107\n"
+        "v_exp_f32_e32 v96, v108\n"
+        "v_exp_f32_e32 v97, v109\n"
+        "v_exp_f32_e32 v98, v114\n"
+        "v_exp_f32_e32 v99, v115\n"
+        "v_exp_f32_e32 v100, v116\n"
+        "v_exp_f32_e32 v101, v117\n"
+        "v_fmaak_f32 v102, v49, v49, 0xc1f00000\n"
+        "v_fmaak_f32 v103, v50, v50, 0xc1f00000\n"
+        "v_fmaak_f32 v104, v51, v51, 0xc1f00000\n"
+        "v_fmaak_f32 v105, v52, v52, 0xc1f00000\n"
+        "v_fma_f32 v40, v40, v57, 0\n"
+        "v_fma_f32 v41, v41, v58, 0\n"
+        "v_fma_f32 v42, v42, v59, 0\n"
+        "v_fma_f32 v43, v43, v60, 0\n"
+        "v_fmaak_f32 v110, v53, v53, 0xc1f00000\n"
+        "v_fmaak_f32 v111, v54, v54, 0xc1f00000\n"
+        "v_fmaak_f32 v112, v55, v55, 0xc1f00000\n"
+        "v_fmaak_f32 v113, v56, v56, 0xc1f00000\n"
+        "v_fmaak_f32 v49, v102, v49, 0xc2200000\n"
+        "v_fmaak_f32 v50, v103, v50, 0xc2200000\n"
+        "v_fmaak_f32 v51, v104, v51, 0xc2200000\n"
+        "v_fmaak_f32 v52, v105, v52, 0xc2200000\n"
+        "v_fmac_f32_e32 v40, v45, v61\n"
+        "v_fmac_f32_e32 v41, v46, v85\n"
+        "v_fmac_f32_e32 v42, v47, v92\n"
+        "v_fmac_f32_e32 v43, v48, v93\n"
+        "v_fmaak_f32 v53, v110, v53, 0xc2200000\n"
+        "v_fmaak_f32 v54, v111, v54, 0xc2200000\n"
+        "v_fmaak_f32 v55, v112, v55, 0xc2200000\n"
+        "v_fmaak_f32 v56, v113, v56, 0xc2200000\n"
+        "v_fmac_f32_e32 v40, v49, v94\n"
+        "v_fmac_f32_e32 v41, v50, v95\n"
+        "v_fmac_f32_e32 v42, v51, v96\n"
+        "v_fmac_f32_e32 v43, v52, v97\n"
+        "v_fmac_f32_e32 v40, v53, v98\n"
+        "v_fmac_f32_e32 v41, v54, v99\n"
+        "v_fmac_f32_e32 v42, v55, v100\n"
+        "v_fmac_f32_e32 v43, v56, v101\n"
+        "v_add_f32_e32 v40, v40, v41\n"
+        "v_add_f32_e32 v41, v42, v43\n"
         "s_sub_u32 %[cnt], %[cnt], 1\n"
-        "v_add_f32_e32 v80, v80, v81\n"
-        "v_cvt_f64_f32_e32 v[80:81], v80\n"
+        "v_add_f32_e32 v40, v40, v41\n"
+        "v_cvt_f64_f32_e32 v[40:41], v40\n"
         "s_cmp_lg_u32 %[cnt], 0\n"
-        "v_add_f64 %[tot], %[tot], v[80:81]\n"
+        "v_add_f64 %[tot], %[tot], v[40:41]\n"
         "s_cbranch_scc1 1b\n"
-        : [tot] "+{v[74:75]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
-        : [ui] "{v84}"(ui), [k] "s"(k)
-        : "v80", "v81", "v82", "v83", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101", "v125", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "v144", "v145", "v146", "v147", "v148", "v149", "v150", "v151", "v152", "v153", "v154", "v155", "v156", "v157", "scc", "memory");
+        : [tot] "+{v[34:35]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
+        : [ui] "{v44}"(ui), [k] "s"(k)
+        : "v40", "v41", "v42", "v43", "v45", "v46", "v47", "v48", "v49", "v50", "v51", "v52", "v53", "v54", "v55", "v56", "v57", "v58", "v59", "v60", "v61", "v85", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101", "v102", "v103", "v104", "v105", "v106", "v107", "v108", "v109", "v110", "v111", "v112", "v113", "v114", "v115", "v116", "v117", "scc", "memory");
 }
 
 // The exact-k variant (KDE_FP32_COMP_EXACT) of the Step IV loop above:
@@ -680,168 +680,168 @@ __device__ __forceinline__ void pair16_loop_r6x_f32(uint32_t addr, int32_t cnt, 
         "s_nop 0\n"
         "s_nop 0\n"
         "1:\n"
-        "v_mov_b32_e32 v83, %[addr]\n"
-        "ds_read_b128 v[78:81], v83\n"
-        "ds_read_b128 v[84:87], v83 offset:16\n"
-        "ds_read_b128 v[88:91], v83 offset:32\n"
-        "ds_read_b128 v[92:95], v83 offset:48\n"
+        "v_mov_b32_e32 v43, %[addr]\n"
+        "ds_read_b128 v[38:41], v43\n"
+        "ds_read_b128 v[44:47], v43 offset:16\n"
+        "ds_read_b128 v[48:51], v43 offset:32\n"
+        "ds_read_b128 v[52:55], v43 offset:48\n"
         "s_add_u32 %[addr], %[addr], 64\n"
         "s_waitcnt lgkmcnt(0)\n"
-        "v_sub_f32_e32 v78, %[ui], v78\n"
-        "v_sub_f32_e32 v79, %[ui], v79\n"
-        "v_sub_f32_e32 v80, %[ui], v80\n"
-        "v_sub_f32_e32 v81, %[ui], v81\n"
-        "v_sub_f32_e32 v83, %[ui], v84\n"
-        "v_sub_f32_e32 v84, %[ui], v85\n"
-        "v_sub_f32_e32 v85, %[ui], v86\n"
-        "v_sub_f32_e32 v86, %[ui], v87\n"
-        "v_sub_f32_e32 v87, %[ui], v88\n"
-        "v_sub_f32_e32 v88, %[ui], v89\n"
-        "v_sub_f32_e32 v89, %[ui], v90\n"
-        "v_sub_f32_e32 v90, %[ui], v91\n"
-        "v_sub_f32_e32 v91, %[ui], v92\n"
-        "v_sub_f32_e32 v92, %[ui], v93\n"
-        "v_sub_f32_e32 v93, %[ui], v94\n"
-        "v_sub_f32_e32 v94, %[ui], v95\n"
-        "v_mul_f32_e32 v95, v78, v78\n"
-        "v_mul_f32_e32 v96, v79, v79\n"
-        "v_mul_f32_e32 v97, v80, v80\n"
-        "v_mul_f32_e32 v98, v81, v81\n"
-        "v_fmaak_f32 v78, v78, v78, 0xc1700000\n"
-        "v_fmaak_f32 v79, v79, v79, 0xc1700000\n"
-        "v_fmaak_f32 v80, v80, v80, 0xc1700000\n"
-        "v_fmaak_f32 v81, v81, v81, 0xc1700000\n"
-        "v_mul_f32_e32 v99, v83, v83\n"
-        "v_mul_f32_e32 v123, v84, v84\n"
-        "v_mul_f32_e32 v130, v85, v85\n"
-        "v_mul_f32_e32 v131, v86, v86\n"
-        "v_mul_f32_e32 v140, %[klo], v95\n"
-        "v_mul_f32_e32 v141, %[klo], v96\n"
-        "v_mul_f32_e32 v142, %[klo], v97\n"
-        "v_mul_f32_e32 v143, %[klo], v98\n"
-        "v_fmaak_f32 v83, v83, v83, 0xc1700000\n"
-        "v_fmaak_f32 v84, v84, v84, 0xc1700000\n"
-        "v_fmaak_f32 v85, v85, v85, 0xc1700000\n"
-        "v_fmaak_f32 v86, v86, v86, 0xc1700000\n"
-        "v_mul_f32_e32 v132, v87, v87\n"
-        "v_mul_f32_e32 v133, v88, v88\n"
-        "v_mul_f32_e32 v134, v89, v89\n"
-        "v_mul_f32_e32 v135, v90, v90\n"
-        "v_fmaak_f32 v78, v78, v95, 0x42340000\n"
-        "v_fmaak_f32 v79, v79, v96, 0x42340000\n"
-        "v_fmaak_f32 v80, v80, v97, 0x42340000\n"
-        "v_fmaak_f32 v81, v81, v98, 0x42340000\n"
-        "v_mul_f32_e32 v144, %[klo], v99\n"
-        "v_mul_f32_e32 v145, %[klo], v123\n"
-        "v_mul_f32_e32 v146, %[klo], v130\n"
-        "v_mul_f32_e32 v147, %[klo], v131\n"
-        "v_fmac_f32_e32 v140, %[khi], v95\n"
-        "v_fmac_f32_e32 v141, %[khi], v96\n"
-        "v_fmac_f32_e32 v142, %[khi], v97\n"
-        "v_fmac_f32_e32 v143, %[khi], v98\n"
-        "v_fmaak_f32 v87, v87, v87, 0xc1700000\n"
-        "v_fmaak_f32 v88, v88, v88, 0xc1700000\n"
-        "v_fmaak_f32 v89, v89, v89, 0xc1700000\n"
-        "v_fmaak_f32 v90, v90, v90, 0xc1700000\n"
-        "v_mul_f32_e32 v136, v91, v91\n"
-        "v_mul_f32_e32 v137, v92, v92\n"
-        "v_mul_f32_e32 v138, v93, v93\n"
-        "v_mul_f32_e32 v139, v94, v94\n"
-        "v_fmaak_f32 v83, v83, v99, 0x42340000\n"
-        "v_fmaak_f32 v84, v84, v123, 0x42340000\n"
-        "v_fmaak_f32 v85, v85, v130, 0x42340000\n"
-        "v_fmaak_f32 v86, v86, v131, 0x42340000\n"
-        "v_mul_f32_e32 v148, %[klo], v132\n"
-        "v_mul_f32_e32 v149, %[klo], v133\n"
-        "v_mul_f32_e32 v150, %[klo], v134\n"
-        "v_mul_f32_e32 v151, %[klo], v135\n"
-        "v_fmaak_f32 v78, v78, v95, 0xc1700000\n"
-        "v_fmaak_f32 v79, v79, v96, 0xc1700000\n"
-        "v_fmaak_f32 v80, v80, v97, 0xc1700000\n"
-        "v_fmaak_f32 v81, v81, v98, 0xc1700000\n"
-        "v_fmac_f32_e32 v144, %[khi], v99\n"
-        "v_fmac_f32_e32 v145, %[khi], v123\n"
-        "v_fmac_f32_e32 v146, %[khi], v130\n"
-        "v_fmac_f32_e32 v147, %[khi], v131\n"
-        "v_exp_f32_e64 v95, -v140\n"
-        "v_exp_f32_e64 v96, -v141\n"
-        "v_exp_f32_e64 v97, -v142\n"
-        "v_exp_f32_e64 v98, -v143\n"
-        "v_fmaak_f32 v91, v91, v91, 0xc1700000\n"
-        "v_fmaak_f32 v92, v92, v92, 0xc1700000\n"
-        "v_fmaak_f32 v93, v93, v93, 0xc1700000\n"
-        "v_fmaak_f32 v94, v94, v94, 0xc1700000\n"
-        "v_fmaak_f32 v87, v87, v132, 0x42340000\n"
-        "v_fmaak_f32 v88, v88, v133, 0x42340000\n"
-        "v_fmaak_f32 v89, v89, v134, 0x42340000\n"
-        "v_fmaak_f32 v90, v90, v135, 0x42340000\n"
-        "v_mul_f32_e32 v152, %[klo], v136\n"
-        "v_mul_f32_e32 v153, %[klo], v137\n"
-        "v_mul_f32_e32 v154, %[klo], v138\n"
-        "v_mul_f32_e32 v155, %[klo], v139\n"
-        "v_fmaak_f32 v83, v83, v99, 0xc1700000\n"
-        "v_fmaak_f32 v84, v84, v123, 0xc1700000\n"
-        "v_fmaak_f32 v85, v85, v130, 0xc1700000\n"
-        "v_fmaak_f32 v86, v86, v131, 0xc1700000\n"
-        "v_fmac_f32_e32 v148, %[khi], v132\n"
-        "v_fmac_f32_e32 v149, %[khi], v133\n"
-        "v_fmac_f32_e32 v150, %[khi], v134\n"
-        "v_fmac_f32_e32 v151, %[khi], v135\n"
-        "v_exp_f32_e64 v99, -v144\n"
-        "v_exp_f32_e64 v123, -v145\n"
-        "v_exp_f32_e64 v130, -v146\n"
-        "v_exp_f32_e64 v131, -v147\n"
-        "v_fmaak_f32 v91, v91, v136, 0x42340000\n"
-        "v_fmaak_f32 v92, v92, v137, 0x42340000\n"
-        "v_fmaak_f32 v93, v93, v138, 0x42340000\n"
-        "v_fmaak_f32 v94, v94, v139, 0x42340000\n"
-        "v_fmaak_f32 v87, v87, v132, 0xc1700000\n"
-        "v_fmaak_f32 v88, v88, v133, 0xc1700000\n"
-        "v_fmaak_f32 v89, v89, v134, 0xc1700000\n"
-        "v_fmaak_f32 v90, v90, v135, 0xc1700000\n"
-        "v_fmac_f32_e32 v152, %[khi], v136\n"
-        "v_fmac_f32_e32 v153, %[khi], v137\n"
-        "v_fmac_f32_e32 v154, %[khi], v138\n"
-        "v_fmac_f32_e32 v155, %[khi], v139\n"
-        "v_exp_f32_e64 v132, -v148\n"
-        "v_exp_f32_e64 v133, -v149\n"
-        "v_exp_f32_e64 v134, -v150\n"
-        "v_exp_f32_e64 v135, -v151\n"
-        "v_fmaak_f32 v91, v91, v136, 0xc1700000\n"
-        "v_fmaak_f32 v92, v92, v137, 0xc1700000\n"
-        "v_fmaak_f32 v93, v93, v138, 0xc1700000\n"
-        "v_fmaak_f32 v94, v94, v139, 0xc1700000\n"
-        "v_exp_f32_e64 v136, -v152\n"
-        "v_exp_f32_e64 v137, -v153\n"
-        "v_exp_f32_e64 v138, -v154\n"
-        "v_exp_f32_e64 v139, -v155\n"
-        "v_fma_f32 v78, v78, v95, 0\n"
-        "v_fma_f32 v79, v79, v96, 0\n"
-        "v_fma_f32 v80, v80, v97, 0\n"
-        "v_fma_f32 v81, v81, v98, 0\n"
-        "v_fmac_f32_e32 v78, v83, v99\n"
-        "v_fmac_f32_e32 v79, v84, v123\n"
-        "v_fmac_f32_e32 v80, v85, v130\n"
-        "v_fmac_f32_e32 v81, v86, v131\n"
-        "v_fmac_f32_e32 v78, v87, v132\n"
-        "v_fmac_f32_e32 v79, v88, v133\n"
-        "v_fmac_f32_e32 v80, v89, v134\n"
-        "v_fmac_f32_e32 v81, v90, v135\n"
-        "v_fmac_f32_e32 v78, v91, v136\n"
-        "v_fmac_f32_e32 v79, v92, v137\n"
-        "v_fmac_f32_e32 v80, v93, v138\n"
-        "v_fmac_f32_e32 v81, v94, v139\n"
-        "v_add_f32_e32 v78, v78, v79\n"
-        "v_add_f32_e32 v79, v80, v81\n"
+        "v_sub_f32_e32 v38, %[ui], v38\n"
+        "v_sub_f32_e32 v39, %[ui], v39\n"
+        "v_sub_f32_e32 v40, %[ui], v40\n"
+        "v_sub_f32_e32 v41, %[ui], v41\n"
+        "v_sub_f32_e32 v43, %[ui], v44\n"
+        "v_sub_f32_e32 v44, %[ui], v45\n"
+        "v_sub_f32_e32 v45, %[ui], v46\n"
+        "v_sub_f32_e32 v46, %[ui], v47\n"
+        "v_sub_f32_e32 v47, %[ui], v48\n"
+        "v_sub_f32_e32 v48, %[ui], v49\n"
+        "v_sub_f32_e32 v49, %[ui], v50\n"
+        "v_sub_f32_e32 v50, %[ui], v51\n"
+        "v_sub_f32_e32 v51, %[ui], v52\n"
+        "v_sub_f32_e32 v52, %[ui], v53\n"
+        "v_sub_f32_e32 v53, %[ui], v54\n"
+        "v_sub_f32_e32 v54, %[ui], v55\n"
+        "v_mul_f32_e32 v55, v38, v38\n"
+        "v_mul_f32_e32 v56, v39, v39\n"
+        "v_mul_f32_e32 v57, v40, v40\n"
+        "v_mul_f32_e32 v58, v41, v41\n"
+        "v_fmaak_f32 v38, v38, v38, 0xc1700000\n"
+        "v_fmaak_f32 v39, v39, v39, 0xc1700000\n"
+        "v_fmaak_f32 v40, v40, v40, 0xc1700000\n"
+        "v_fmaak_f32 v41, v41, v41, 0xc1700000\n"
+        "v_mul_f32_e32 v59, v43, v43\n"
+        "v_mul_f32_e32 v83, v44, v44\n"
+        "v_mul_f32_e32 v90, v45, v45\n"
+        "v_mul_f32_e32 v91, v46, v46\n"
+        "v_mul_f32_e32 v100, %[klo], v55\n"
+        "v_mul_f32_e32 v101, %[klo], v56\n"
+        "v_mul_f32_e32 v102, %[klo], v57\n"
+        "v_mul_f32_e32 v103, %[klo], v58\n"
+        "v_fmaak_f32 v43, v43, v43, 0xc1700000\n"
+        "v_fmaak_f32 v44, v44, v44, 0xc1700000\n"
+        "v_fmaak_f32 v45, v45, v45, 0xc1700000\n"
+        "v_fmaak_f32 v46, v46, v46, 0xc1700000\n"
+        "v_mul_f32_e32 v92, v47, v47\n"
+        "v_mul_f32_e32 v93, v48, v48\n"
+        "v_mul_f32_e32 v94, v49, v49\n"
+        "v_mul_f32_e32 v95, v50, v50\n"
+        "v_fmaak_f32 v38, v38, v55, 0x42340000\n"
+        "v_fmaak_f32 v39, v39, v56, 0x42340000\n"
+        "v_fmaak_f32 v40, v40, v57, 0x42340000\n"
+        "v_fmaak_f32 v41, v41, v58, 0x42340000\n"
+        "v_mul_f32_e32 v104, %[klo], v59\n"
+        "v_mul_f32_e32 v105, %[klo], v83\n"
+        "v_mul_f32_e32 v106, %[klo], v90\n"
+        "v_mul_f32_e32 v107, %[klo], v91\n"
+        "v_fmac_f32_e32 v100, %[khi], v55\n"
+        "v_fmac_f32_e32 v101, %[khi], v56\n"
+        "v_fmac_f32_e32 v102, %[khi], v57\n"
+        "v_fmac_f32_e32 v103, %[khi], v58\n"
+        "v_fmaak_f32 v47, v47, v47, 0xc1700000\n"
+        "v_fmaak_f32 v48, v48, v48, 0xc1700000\n"
+        "v_fmaak_f32 v49, v49, v49, 0xc1700000\n"
+        "v_fmaak_f32 v50, v50, v50, 0xc1700000\n"
+        "v_mul_f32_e32 v96, v51, v51\n"
+        "v_mul_f32_e32 v97, v52, v52\n"
+        "v_mul_f32_e32 v98, v53, v53\n"
+        "v_mul_f32_e32 v99, v54, v54\n"
+        "v_fmaak_f32 v43, v43, v59, 0x42340000\n"
+        "v_fmaak_f32 v44, v44, v83, 0x42340000\n"
+        "v_fmaak_f32 v45, v45, v90, 0x42340000\n"
+        "v_fmaak_f32 v46, v46, v91, 0x42340000\n"
+        "v_mul_f32_e32 v108, %[klo], v92\n"
+        "v_mul_f32_e32 v109, %[klo], v93\n"
+        "v_mul_f32_e32 v110, %[klo], v94\n"
+        "v_mul_f32_e32 v111, %[klo], v95\n"
+        "v_fmaak_f32 v38, v38, v55, 0xc1700000\n"
+        "v_fmaak_f32 v39, v39, v56, 0xc1700000\n"
+        "v_fmaak_f32 v40, v40, v57, 0xc1700000\n"
+        "v_fmaak_f32 v41, v41, v58, 0xc1700000\n"
+        "v_fmac_f32_e32 v104, %[khi], v59\n"
+        "v_fmac_f32_e32 v105, %[khi], v83\n"
+        "v_fmac_f32_e32 v106, %[khi], v90\n"
+        "v_fmac_f32_e32 v107, %[khi], v91\n"
+        "v_exp_f32_e64 v55, -v100\n"
+        "v_exp_f32_e64 v56, -v101\n"
+        "v_exp_f32_e64 v57, -v102\n"
+        "v_exp_f32_e64 v58, -v103\n"
+        "v_fmaak_f32 v51, v51, v51, 0xc1700000\n"
+        "v_fmaak_f32 v52, v52, v52, 0xc1700000\n"
+        "v_fmaak_f32 v53, v53, v53, 0xc1700000\n"
+        "v_fmaak_f32 v54, v54, v54, 0xc1700000\n"
+        "v_fmaak_f32 v47, v47, v92, 0x42340000\n"
+        "v_fmaak_f32 v48, v48, v93, 0x42340000\n"
+        "v_fmaak_f32 v49, v49, v94, 0x42340000\n"
+        "v_fmaak_f32 v50, v50, v95, 0x42340000\n"
+        "v_mul_f32_e32 v112, %[klo], v96\n"
+        "v_mul_f32_e32 v113, %[klo], v97\n"
+        "v_mul_f32_e32 v114, %[klo], v98\n"
+        "v_mul_f32_e32 v115, %[klo], v99\n"
+        "v_fmaak_f32 v43, v43, v59, 0xc1700000\n"
+        "v_fmaak_f32 v44, v44, v83, 0xc1700000\n"
+        "v_fmaak_f32 v45, v45, v90, 0xc1700000\n"
+        "v_fmaak_f32 v46, v46, v91, 0xc1700000\n"
+        "v_fmac_f32_e32 v108, %[khi], v92\n"
+        "v_fmac_f32_e32 v109, %[khi], v93\n"
+        "v_fmac_f32_e32 v110, %[khi], v94\n"
+        "v_fmac_f32_e32 v111, %[khi], v95\n"
+        "v_exp_f32_e64 v59, -v104\n"
+        "v_exp_f32_e64 v83, -v105\n"
+        "v_exp_f32_e64 v90, -v106\n"
+        "v_exp_f32_e64 v91, -v107\n"
+        "v_fmaak_f32 v51, v51, v96, 0x42340000\n"
+        "v_fmaak_f32 v52, v52, v97, 0x42340000\n"
+        "v_fmaak_f32 v53, v53, v98, 0x42340000\n"
+        "v_fmaak_f32 v54, v54, v99, 0x42340000\n"
+        "v_fmaak_f32 v47, v47, v92, 0xc1700000\n"
+        "v_fmaak_f32 v48, v48, v93, 0xc1700000\n"
+        "v_fmaak_f32 v49, v49, v94, 0xc1700000\n"
+        "v_fmaak_f32 v50, v50, v95, 0xc1700000\n"
+        "v_fmac_f32_e32 v112, %[khi], v96\n"
+        "v_fmac_f32_e32 v113, %[khi], v97\n"
+        "v_fmac_f32_e32 v114, %[khi], v98\n"
+        "v_fmac_f32_e32 v115, %[khi], v99\n"
+        "v_exp_f32_e64 v92, -v108\n"
+        "v_exp_f32_e64 v93, -v109\n"
+        "v_exp_f32_e64 v94, -v110\n"
+        "v_exp_f32_e64 v95, -v111\n"
+        "v_fmaak_f32 v51, v51, v96, 0xc1700000\n"
+        "v_fmaak_f32 v52, v52, v97, 0xc1700000\n"
+        "v_fmaak_f32 v53, v53, v98, 0xc1700000\n"
+        "v_fmaak_f32 v54, v54, v99, 0xc1700000\n"
+        "v_exp_f32_e64 v96, -v112\n"
+        "v_exp_f32_e64 v97, -v113\n"
+        "v_exp_f32_e64 v98, -v114\n"
+        "v_exp_f32_e64 v99, -v115\n"
+        "v_fma_f32 v38, v38, v55, 0\n"
+        "v_fma_f32 v39, v39, v56, 0\n"
+        "v_fma_f32 v40, v40, v57, 0\n"
+        "v_fma_f32 v41, v41, v58, 0\n"
+        "v_fmac_f32_e32 v38, v43, v59\n"
+        "v_fmac_f32_e32 v39, v44, v83\n"
+        "v_fmac_f32_e32 v40, v45, v90\n"
+        "v_fmac_f32_e32 v41, v46, v91\n"
+        "v_fmac_f32_e32 v38, v47, v92\n"
+        "v_fmac_f32_e32 v39, v48, v93\n"
+        "v_fmac_f32_e32 v40, v49, v94\n"
+        "v_fmac_f32_e32 v41, v50, v95\n"
+        "v_fmac_f32_e32 v38, v51, v96\n"
+        "v_fmac_f32_e32 v39, v52, v97\n"
+        "v_fmac_f32_e32 v40, v53, v98\n"
+        "v_fmac_f32_e32 v41, v54, v99\n"
+        "v_add_f32_e32 v38, v38, v39\n"
+        "v_add_f32_e32 v39, v40, v41\n"
         "s_sub_u32 %[cnt], %[cnt], 1\n"
-        "v_add_f32_e32 v78, v78, v79\n"
-        "v_cvt_f64_f32_e32 v[78:79], v78\n"
+        "v_add_f32_e32 v38, v38, v39\n"
+        "v_cvt_f64_f32_e32 v[38:39], v38\n"
         "s_cmp_lg_u32 %[cnt], 0\n"
-        "v_add_f64 %[tot], %[tot], v[78:79]\n"
+        "v_add_f64 %[tot], %[tot], v[38:39]\n"
         "s_cbranch_scc1 1b\n"
-        : [tot] "+{v[72:73]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
-        : [ui] "{v82}"(ui), [khi] "s"(khi), [klo] "s"(klo)
-        : "v78", "v79", "v80", "v81", "v83", "v84", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v123", "v130", "v131", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "v144", "v145", "v146", "v147", "v148", "v149", "v150", "v151", "v152", "v153", "v154", "v155", "scc", "memory");
+        : [tot] "+{v[32:33]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
+        : [ui] "{v42}"(ui), [khi] "s"(khi), [klo] "s"(klo)
+        : "v38", "v39", "v40", "v41", "v43", "v44", "v45", "v46", "v47", "v48", "v49", "v50", "v51", "v52", "v53", "v54", "v55", "v56", "v57", "v58", "v59", "v83", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101", "v102", "v103", "v104", "v105", "v106", "v107", "v108", "v109", "v110", "v111", "v112", "v113", "v114", "v115", "scc", "memory");
 }
 
 // The exact-k variant of the Step VI loop: as above with
@@ -855,152 +855,152 @@ __device__ __forceinline__ void pair16_loop_r4x_f32(uint32_t addr, int32_t cnt, 
         "s_nop 0\n"
         "s_nop 0\n"
         "1:\n"
-        "v_mov_b32_e32 v83, %[addr]\n"
-        "ds_read_b128 v[78:81], v83\n"
-        "ds_read_b128 v[84:87], v83 offset:16\n"
-        "ds_read_b128 v[88:91], v83 offset:32\n"
-        "ds_read_b128 v[92:95], v83 offset:48\n"
+        "v_mov_b32_e32 v43, %[addr]\n"
+        "ds_read_b128 v[38:41], v43\n"
+        "ds_read_b128 v[44:47], v43 offset:16\n"
+        "ds_read_b128 v[48:51], v43 offset:32\n"
+        "ds_read_b128 v[52:55], v43 offset:48\n"
         "s_add_u32 %[addr], %[addr], 64\n"
         "s_waitcnt lgkmcnt(0)\n"
-        "v_sub_f32_e32 v78, %[ui], v78\n"
-        "v_sub_f32_e32 v79, %[ui], v79\n"
-        "v_sub_f32_e32 v80, %[ui], v80\n"
-        "v_sub_f32_e32 v81, %[ui], v81\n"
-        "v_sub_f32_e32 v83, %[ui], v84\n"
-        "v_sub_f32_e32 v84, %[ui], v85\n"
-        "v_sub_f32_e32 v85, %[ui], v86\n"
-        "v_sub_f32_e32 v86, %[ui], v87\n"
-        "v_sub_f32_e32 v87, %[ui], v88\n"
-        "v_sub_f32_e32 v88, %[ui], v89\n"
-        "v_sub_f32_e32 v89, %[ui], v90\n"
-        "v_sub_f32_e32 v90, %[ui], v91\n"
-        "v_sub_f32_e32 v91, %[ui], v92\n"
-        "v_sub_f32_e32 v92, %[ui], v93\n"
-        "v_sub_f32_e32 v93, %[ui], v94\n"
-        "v_sub_f32_e32 v94, %[ui], v95\n"
-        "v_mul_f32_e32 v95, v78, v78\n"
-        "v_mul_f32_e32 v96, v79, v79\n"
-        "v_mul_f32_e32 v97, v80, v80\n"
-        "v_mul_f32_e32 v98, v81, v81\n"
-        "v_mul_f32_e32 v99, v83, v83\n"
-        "v_mul_f32_e32 v123, v84, v84\n"
-        "v_mul_f32_e32 v130, v85, v85\n"
-        "v_mul_f32_e32 v131, v86, v86\n"
-        "v_mul_f32_e32 v140, %[klo], v95\n"
-        "v_mul_f32_e32 v141, %[klo], v96\n"
-        "v_mul_f32_e32 v142, %[klo], v97\n"
-        "v_mul_f32_e32 v143, %[klo], v98\n"
-        "v_fmaak_f32 v78, v78, v78, 0xc0c00000\n"
-        "v_fmaak_f32 v79, v79, v79, 0xc0c00000\n"
-        "v_fmaak_f32 v80, v80, v80, 0xc0c00000\n"
-        "v_fmaak_f32 v81, v81, v81, 0xc0c00000\n"
-        "v_mul_f32_e32 v132, v87, v87\n"
-        "v_mul_f32_e32 v133, v88, v88\n"
-        "v_mul_f32_e32 v134, v89, v89\n"
-        "v_mul_f32_e32 v135, v90, v90\n"
-        "v_mul_f32_e32 v144, %[klo], v99\n"
-        "v_mul_f32_e32 v145, %[klo], v123\n"
-        "v_mul_f32_e32 v146, %[klo], v130\n"
-        "v_mul_f32_e32 v147, %[klo], v131\n"
-        "v_fmac_f32_e32 v140, %[khi], v95\n"
-        "v_fmac_f32_e32 v141, %[khi], v96\n"
-        "v_fmac_f32_e32 v142, %[khi], v97\n"
-        "v_fmac_f32_e32 v143, %[khi], v98\n"
-        "v_fmaak_f32 v83, v83, v83, 0xc0c00000\n"
-        "v_fmaak_f32 v84, v84, v84, 0xc0c00000\n"
-        "v_fmaak_f32 v85, v85, v85, 0xc0c00000\n"
-        "v_fmaak_f32 v86, v86, v86, 0xc0c00000\n"
-        "v_mul_f32_e32 v136, v91, v91\n"
-        "v_mul_f32_e32 v137, v92, v92\n"
-        "v_mul_f32_e32 v138, v93, v93\n"
-        "v_mul_f32_e32 v139, v94, v94\n"
-        "v_fmaak_f32 v78, v78, v95, 0x40400000\n"
-        "v_fmaak_f32 v79, v79, v96, 0x40400000\n"
-        "v_fmaak_f32 v80, v80, v97, 0x40400000\n"
-        "v_fmaak_f32 v81, v81, v98, 0x40400000\n"
-        "v_mul_f32_e32 v148, %[klo], v132\n"
-        "v_mul_f32_e32 v149, %[klo], v133\n"
-        "v_mul_f32_e32 v150, %[klo], v134\n"
-        "v_mul_f32_e32 v151, %[klo], v135\n"
-        "v_fmac_f32_e32 v144, %[khi], v99\n"
-        "v_fmac_f32_e32 v145, %[khi], v123\n"
-        "v_fmac_f32_e32 v146, %[khi], v130\n"
-        "v_fmac_f32_e32 v147, %[khi], v131\n"
-        "v_exp_f32_e64 v95, -v140\n"
-        "v_exp_f32_e64 v96, -v141\n"
-        "v_exp_f32_e64 v97, -v142\n"
-        "v_exp_f32_e64 v98, -v143\n"
-        "v_fmaak_f32 v87, v87, v87, 0xc0c00000\n"
-        "v_fmaak_f32 v88, v88, v88, 0xc0c00000\n"
-        "v_fmaak_f32 v89, v89, v89, 0xc0c00000\n"
-        "v_fmaak_f32 v90, v90, v90, 0xc0c00000\n"
-        "v_fmaak_f32 v83, v83, v99, 0x40400000\n"
-        "v_fmaak_f32 v84, v84, v123, 0x40400000\n"
-        "v_fmaak_f32 v85, v85, v130, 0x40400000\n"
-        "v_fmaak_f32 v86, v86, v131, 0x40400000\n"
-        "v_mul_f32_e32 v152, %[klo], v136\n"
-        "v_mul_f32_e32 v153, %[klo], v137\n"
-        "v_mul_f32_e32 v154, %[klo], v138\n"
-        "v_mul_f32_e32 v155, %[klo], v139\n"
-        "v_fmac_f32_e32 v148, %[khi], v132\n"
-        "v_fmac_f32_e32 v149, %[khi], v133\n"
-        "v_fmac_f32_e32 v150, %[khi], v134\n"
-        "v_fmac_f32_e32 v151, %[khi], v135\n"
-        "v_exp_f32_e64 v99, -v144\n"
-        "v_exp_f32_e64 v123, -v145\n"
-        "v_exp_f32_e64 v130, -v146\n"
-        "v_exp_f32_e64 v131, -v147\n"
-        "v_fmaak_f32 v91, v91, v91, 0xc0c00000\n"
-        "v_fmaak_f32 v92, v92, v92, 0xc0c00000\n"
-        "v_fmaak_f32 v93, v93, v93, 0xc0c00000\n"
-        "v_fmaak_f32 v94, v94, v94, 0xc0c00000\n"
-        "v_fmaak_f32 v87, v87, v132, 0x40400000\n"
-        "v_fmaak_f32 v88, v88, v133, 0x40400000\n"
-        "v_fmaak_f32 v89, v89, v134, 0x40400000\n"
-        "v_fmaak_f32 v90, v90, v135, 0x40400000\n"
-        "v_fmac_f32_e32 v152, %[khi], v136\n"
-        "v_fmac_f32_e32 v153, %[khi], v137\n"
-        "v_fmac_f32_e32 v154, %[khi], v138\n"
-        "v_fmac_f32_e32 v155, %[khi], v139\n"
-        "v_exp_f32_e64 v132, -v148\n"
-        "v_exp_f32_e64 v133, -v149\n"
-        "v_exp_f32_e64 v134, -v150\n"
-        "v_exp_f32_e64 v135, -v151\n"
-        "v_fmaak_f32 v91, v91, v136, 0x40400000\n"
-        "v_fmaak_f32 v92, v92, v137, 0x40400000\n"
-        "v_fmaak_f32 v93, v93, v138, 0x40400000\n"
-        "v_fmaak_f32 v94, v94, v139, 0x40400000\n"
-        "v_exp_f32_e64 v136, -v152\n"
-        "v_exp_f32_e64 v137, -v153\n"
-        "v_exp_f32_e64 v138, -v154\n"
-        "v_exp_f32_e64 v139, -v155\n"
-        "v_fma_f32 v78, v78, v95, 0\n"
-        "v_fma_f32 v79, v79, v96, 0\n"
-        "v_fma_f32 v80, v80, v97, 0\n"
-        "v_fma_f32 v81, v81, v98, 0\n"
-        "v_fmac_f32_e32 v78, v83, v99\n"
-        "v_fmac_f32_e32 v79, v84, v123\n"
-        "v_fmac_f32_e32 v80, v85, v130\n"
-        "v_fmac_f32_e32 v81, v86, v131\n"
-        "v_fmac_f32_e32 v78, v87, v132\n"
-        "v_fmac_f32_e32 v79, v88, v133\n"
-        "v_fmac_f32_e32 v80, v89, v134\n"
-        "v_fmac_f32_e32 v81, v90, v135\n"
-        "v_fmac_f32_e32 v78, v91, v136\n"
-        "v_fmac_f32_e32 v79, v92, v137\n"
-        "v_fmac_f32_e32 v80, v93, v138\n"
-        "v_fmac_f32_e32 v81, v94, v139\n"
-        "v_add_f32_e32 v78, v78, v79\n"
-        "v_add_f32_e32 v79, v80, v81\n"
+        "v_sub_f32_e32 v38, %[ui], v38\n"
+        "v_sub_f32_e32 v39, %[ui], v39\n"
+        "v_sub_f32_e32 v40, %[ui], v40\n"
+        "v_sub_f32_e32 v41, %[ui], v41\n"
+        "v_sub_f32_e32 v43, %[ui], v44\n"
+        "v_sub_f32_e32 v44, %[ui], v45\n"
+        "v_sub_f32_e32 v45, %[ui], v46\n"
+        "v_sub_f32_e32 v46, %[ui], v47\n"
+        "v_sub_f32_e32 v47, %[ui], v48\n"
+        "v_sub_f32_e32 v48, %[ui], v49\n"
+        "v_sub_f32_e32 v49, %[ui], v50\n"
+        "v_sub_f32_e32 v50, %[ui], v51\n"
+        "v_sub_f32_e32 v51, %[ui], v52\n"
+        "v_sub_f32_e32 v52, %[ui], v53\n"
+        "v_sub_f32_e32 v53, %[ui], v54\n"
+        "v_sub_f32_e32 v54, %[ui], v55\n"
+        "v_mul_f32_e32 v55, v38, v38\n"
+        "v_mul_f32_e32 v56, v39, v39\n"
+        "v_mul_f32_e32 v57, v40, v40\n"
+        "v_mul_f32_e32 v58, v41, v41\n"
+        "v_mul_f32_e32 v59, v43, v43\n"
+        "v_mul_f32_e32 v83, v44, v44\n"
+        "v_mul_f32_e32 v90, v45, v45\n"
+        "v_mul_f32_e32 v91, v46, v46\n"
+        "v_mul_f32_e32 v100, %[klo], v55\n"
+        "v_mul_f32_e32 v101, %[klo], v56\n"
+        "v_mul_f32_e32 v102, %[klo], v57\n"
+        "v_mul_f32_e32 v103, %[klo], v58\n"
+        "v_fmaak_f32 v38, v38, v38, 0xc0c00000\n"
+        "v_fmaak_f32 v39, v39, v39, 0xc0c00000\n"
+        "v_fmaak_f32 v40, v40, v40, 0xc0c00000\n"
+        "v_fmaak_f32 v41, v41, v41, 0xc0c00000\n"
+        "v_mul_f32_e32 v92, v47, v47\n"
+        "v_mul_f32_e32 v93, v48, v48\n"
+        "v_mul_f32_e32 v94, v49, v49\n"
+        "v_mul_f32_e32 v95, v50, v50\n"
+        "v_mul_f32_e32 v104, %[klo], v59\n"
+        "v_mul_f32_e32 v105, %[klo], v83\n"
+        "v_mul_f32_e32 v106, %[klo], v90\n"
+        "v_mul_f32_e32 v107, %[klo], v91\n"
+        "v_fmac_f32_e32 v100, %[khi], v55\n"
+        "v_fmac_f32_e32 v101, %[khi], v56\n"
+        "v_fmac_f32_e32 v102, %[khi], v57\n"
+        "v_fmac_f32_e32 v103, %[khi], v58\n"
+        "v_fmaak_f32 v43, v43, v43, 0xc0c00000\n"
+        "v_fmaak_f32 v44, v44, v44, 0xc0c00000\n"
+        "v_fmaak_f32 v45, v45, v45, 0xc0c00000\n"
+        "v_fmaak_f32 v46, v46, v46, 0xc0c00000\n"
+        "v_mul_f32_e32 v96, v51, v51\n"
+        "v_mul_f32_e32 v97, v52, v52\n"
+        "v_mul_f32_e32 v98, v53, v53\n"
+        "v_mul_f32_e32 v99, v54, v54\n"
+        "v_fmaak_f32 v38, v38, v55, 0x40400000\n"
+        "v_fmaak_f32 v39, v39, v56, 0x40400000\n"
+        "v_fmaak_f32 v40, v40, v57, 0x40400000\n"
+        "v_fmaak_f32 v41, v41, v58, 0x40400000\n"
+        "v_mul_f32_e32 v108, %[klo], v92\n"
+        "v_mul_f32_e32 v109, %[klo], v93\n"
+        "v_mul_f32_e32 v110, %[klo], v94\n"
+        "v_mul_f32_e32 v111, %[klo], v95\n"
+        "v_fmac_f32_e32 v104, %[khi], v59\n"
+        "v_fmac_f32_e32 v105, %[khi], v83\n"
+        "v_fmac_f32_e32 v106, %[khi], v90\n"
+        "v_fmac_f32_e32 v107, %[khi], v91\n"
+        "v_exp_f32_e64 v55, -v100\n"
+        "v_exp_f32_e64 v56, -v101\n"
+        "v_exp_f32_e64 v57, -v102\n"
+        "v_exp_f32_e64 v58, -v103\n"
+        "v_fmaak_f32 v47, v47, v47, 0xc0c00000\n"
+        "v_fmaak_f32 v48, v48, v48, 0xc0c00000\n"
+        "v_fmaak_f32 v49, v49, v49, 0xc0c00000\n"
+        "v_fmaak_f32 v50, v50, v50, 0xc0c00000\n"
+        "v_fmaak_f32 v43, v43, v59, 0x40400000\n"
+        "v_fmaak_f32 v44, v44, v83, 0x40400000\n"
+        "v_fmaak_f32 v45, v45, v90, 0x40400000\n"
+        "v_fmaak_f32 v46, v46, v91, 0x40400000\n"
+        "v_mul_f32_e32 v112, %[klo], v96\n"
+        "v_mul_f32_e32 v113, %[klo], v97\n"
+        "v_mul_f32_e32 v114, %[klo], v98\n"
+        "v_mul_f32_e32 v115, %[klo], v99\n"
+        "v_fmac_f32_e32 v108, %[khi], v92\n"
+        "v_fmac_f32_e32 v109, %[khi], v93\n"
+        "v_fmac_f32_e32 v110, %[khi], v94\n"
+        "v_fmac_f32_e32 v111, %[khi], v95\n"
+        "v_exp_f32_e64 v59, -v104\n"
+        "v_exp_f32_e64 v83, -v105\n"
+        "v_exp_f32_e64 v90, -v106\n"
+        "v_exp_f32_e64 v91, -v107\n"
+        "v_fmaak_f32 v51, v51, v51, 0xc0c00000\n"
+        "v_fmaak_f32 v52, v52, v52, 0xc0c00000\n"
+        "v_fmaak_f32 v53, v53, v53, 0xc0c00000\n"
+        "v_fmaak_f32 v54, v54, v54, 0xc0c00000\n"
+        "v_fmaak_f32 v47, v47, v92, 0x40400000\n"
+        "v_fmaak_f32 v48, v48, v93, 0x40400000\n"
+        "v_fmaak_f32 v49, v49, v94, 0x40400000\n"
+        "v_fmaak_f32 v50, v50, v95, 0x40400000\n"
+        "v_fmac_f32_e32 v112, %[khi], v96\n"
+        "v_fmac_f32_e32 v113, %[khi], v97\n"
+        "v_fmac_f32_e32 v114, %[khi], v98\n"
+        "v_fmac_f32_e32 v115, %[khi], v99\n"
+        "v_exp_f32_e64 v92, -v108\n"
+        "v_exp_f32_e64 v93, -v109\n"
+        "v_exp_f32_e64 v94, -v110\n"
+        "v_exp_f32_e64 v95, -v111\n"
+        "v_fmaak_f32 v51, v51, v96, 0x40400000\n"
+        "v_fmaak_f32 v52, v52, v97, 0x40400000\n"
+        "v_fmaak_f32 v53, v53, v98, 0x40400000\n"
+        "v_fmaak_f32 v54, v54, v99, 0x40400000\n"
+        "v_exp_f32_e64 v96, -v112\n"
+        "v_exp_f32_e64 v97, -v113\n"
+        "v_exp_f32_e64 v98, -v114\n"
+        "v_exp_f32_e64 v99, -v115\n"
+        "v_fma_f32 v38, v38, v55, 0\n"
+        "v_fma_f32 v39, v39, v56, 0\n"
+        "v_fma_f32 v40, v40, v57, 0\n"
+        "v_fma_f32 v41, v41, v58, 0\n"
+        "v_fmac_f32_e32 v38, v43, v59\n"
+        "v_fmac_f32_e32 v39, v44, v83\n"
+        "v_fmac_f32_e32 v40, v45, v90\n"
+        "v_fmac_f32_e32 v41, v46, v91\n"
+        "v_fmac_f32_e32 v38, v47, v92\n"
+        "v_fmac_f32_e32 v39, v48, v93\n"
+        "v_fmac_f32_e32 v40, v49, v94\n"
+        "v_fmac_f32_e32 v41, v50, v95\n"
+        "v_fmac_f32_e32 v38, v51, v96\n"
+        "v_fmac_f32_e32 v39, v52, v97\n"
+        "v_fmac_f32_e32 v40, v53, v98\n"
+        "v_fmac_f32_e32 v41, v54, v99\n"
+        "v_add_f32_e32 v38, v38, v39\n"
+        "v_add_f32_e32 v39, v40, v41\n"
         "s_sub_u32 %[cnt], %[cnt], 1\n"
-        "v_add_f32_e32 v78, v78, v79\n"
-        "v_cvt_f64_f32_e32 v[78:79], v78\n"
+        "v_add_f32_e32 v38, v38, v39\n"
+        "v_cvt_f64_f32_e32 v[38:39], v38\n"
         "s_cmp_lg_u32 %[cnt], 0\n"
-        "v_add_f64 %[tot], %[tot], v[78:79]\n"
+        "v_add_f64 %[tot], %[tot], v[38:39]\n"
         "s_cbranch_scc1 1b\n"
-        : [tot] "+{v[72:73]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
-        : [ui] "{v82}"(ui), [khi] "s"(khi), [klo] "s"(klo)
-        : "v78", "v79", "v80", "v81", "v83", "v84", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v123", "v130", "v131", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "v144", "v145", "v146", "v147", "v148", "v149", "v150", "v151", "v152", "v153", "v154", "v155", "scc", "memory");
+        : [tot] "+{v[32:33]}"(tot), [addr] "+s"(addr), [cnt] "+s"(cnt)
+        : [ui] "{v42}"(ui), [khi] "s"(khi), [klo] "s"(klo)
+        : "v38", "v39", "v40", "v41", "v43", "v44", "v45", "v46", "v47", "v48", "v49", "v50", "v51", "v52", "v53", "v54", "v55", "v56", "v57", "v58", "v59", "v83", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101", "v102", "v103", "v104", "v105", "v106", "v107", "v108", "v109", "v110", "v111", "v112", "v113", "v114", "v115", "scc", "memory");
 }
 
 // Columns [c0, c1) of pair item cb of the row block starting at row r0
@@ -1664,8 +1664,8 @@ __device__ void complete_items(const LaunchArgs& A, int32_t ds, const View& d, S
 // finishes its item and takes the next ticket, and a block without tickets
 // has counted everything: every stage counter reaches its item count and
 // every flag is published.
-template <int PREC, int R, int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_persistent(LaunchArgs A) {
+template <int PREC, int R, int BLOCK, int WAVES>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_persistent(LaunchArgs A) {
     using TileT = typename std::conditional<PREC >= 1 && PREC <= 3, float, double>::type;
     __shared__ __align__(16) TileT tile[TJ];
     __shared__ double red[BLOCK / WAVE];
@@ -1880,76 +1880,85 @@ hipError_t launch_results(const State* states, const int32_t* outmap, int64_t n_
     return hipGetLastError();
 }
 
-template <int PREC, int R>
+template <int PREC, int R, int WAVES>
 static hipError_t launch_one(int grid, hipStream_t s, const LaunchArgs& a) {
-    hipLaunchKernelGGL((k_persistent<PREC, R, 256>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_persistent<PREC, R, 256, WAVES>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-template <int PREC, int R>
+template <int PREC, int R, int WAVES>
 static hipError_t occ_one(int* blocks) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_persistent<PREC, R, 256>, 256, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_persistent<PREC, R, 256, WAVES>, 256, 0);
 }
 
-hipError_t launch_persistent(int prec, int R, int grid, hipStream_t s, const LaunchArgs& a) {
+// Every (precision, R) has a kernel held to three waves per SIMD (at most
+// 168 VGPRs); the default precision at R = 1 also has one held to four (at
+// most 128 VGPRs, some spilled outside the pair loops), the faster one for
+// large samples.
+bool wide_available(int prec, int R) { return prec == 1 && R == 1; }
+
+hipError_t launch_persistent(int prec, int R, bool wide, int grid, hipStream_t s, const LaunchArgs& a) {
+    if (wide) return wide_available(prec, R) ? launch_one<1, 1, 4>(grid, s, a) : hipErrorInvalidValue;
     switch (prec * 8 + R) {
-    case 0 * 8 + 1: return launch_one<0, 1>(grid, s, a);
-    case 0 * 8 + 2: return launch_one<0, 2>(grid, s, a);
-    case 0 * 8 + 4: return launch_one<0, 4>(grid, s, a);
-    case 1 * 8 + 1: return launch_one<1, 1>(grid, s, a);
-    case 1 * 8 + 2: return launch_one<1, 2>(grid, s, a);
-    case 1 * 8 + 4: return launch_one<1, 4>(grid, s, a);
-    case 2 * 8 + 1: return launch_one<2, 1>(grid, s, a);
-    case 2 * 8 + 2: return launch_one<2, 2>(grid, s, a);
-    case 2 * 8 + 4: return launch_one<2, 4>(grid, s, a);
-    case 3 * 8 + 1: return launch_one<3, 1>(grid, s, a);
-    case 3 * 8 + 2: return launch_one<3, 2>(grid, s, a);
-    case 3 * 8 + 4: return launch_one<3, 4>(grid, s, a);
-    case 4 * 8 + 1: return launch_one<4, 1>(grid, s, a);
-    case 4 * 8 + 2: return launch_one<4, 2>(grid, s, a);
-    case 4 * 8 + 4: return launch_one<4, 4>(grid, s, a);
+    case 0 * 8 + 1: return launch_one<0, 1, 3>(grid, s, a);
+    case 0 * 8 + 2: return launch_one<0, 2, 3>(grid, s, a);
+    case 0 * 8 + 4: return launch_one<0, 4, 3>(grid, s, a);
+    case 1 * 8 + 1: return launch_one<1, 1, 3>(grid, s, a);
+    case 1 * 8 + 2: return launch_one<1, 2, 3>(grid, s, a);
+    case 1 * 8 + 4: return launch_one<1, 4, 3>(grid, s, a);
+    case 2 * 8 + 1: return launch_one<2, 1, 3>(grid, s, a);
+    case 2 * 8 + 2: return launch_one<2, 2, 3>(grid, s, a);
+    case 2 * 8 + 4: return launch_one<2, 4, 3>(grid, s, a);
+    case 3 * 8 + 1: return launch_one<3, 1, 3>(grid, s, a);
+    case 3 * 8 + 2: return launch_one<3, 2, 3>(grid, s, a);
+    case 3 * 8 + 4: return launch_one<3, 4, 3>(grid, s, a);
+    case 4 * 8 + 1: return launch_one<4, 1, 3>(grid, s, a);
+    case 4 * 8 + 2: return launch_one<4, 2, 3>(grid, s, a);
+    case 4 * 8 + 4: return launch_one<4, 4, 3>(grid, s, a);
     default: return hipErrorInvalidValue;
     }
 }
 
-const void* persistent_kernel(int prec, int R) {
+const void* persistent_kernel(int prec, int R, bool wide) {
+    if (wide) return wide_available(prec, R) ? (const void*)k_persistent<1, 1, 256, 4> : nullptr;
     switch (prec * 8 + R) {
-    case 0 * 8 + 1: return (const void*)k_persistent<0, 1, 256>;
-    case 0 * 8 + 2: return (const void*)k_persistent<0, 2, 256>;
-    case 0 * 8 + 4: return (const void*)k_persistent<0, 4, 256>;
-    case 1 * 8 + 1: return (const void*)k_persistent<1, 1, 256>;
-    case 1 * 8 + 2: return (const void*)k_persistent<1, 2, 256>;
-    case 1 * 8 + 4: return (const void*)k_persistent<1, 4, 256>;
-    case 2 * 8 + 1: return (const void*)k_persistent<2, 1, 256>;
-    case 2 * 8 + 2: return (const void*)k_persistent<2, 2, 256>;
-    case 2 * 8 + 4: return (const void*)k_persistent<2, 4, 256>;
-    case 3 * 8 + 1: return (const void*)k_persistent<3, 1, 256>;
-    case 3 * 8 + 2: return (const void*)k_persistent<3, 2, 256>;
-    case 3 * 8 + 4: return (const void*)k_persistent<3, 4, 256>;
-    case 4 * 8 + 1: return (const void*)k_persistent<4, 1, 256>;
-    case 4 * 8 + 2: return (const void*)k_persistent<4, 2, 256>;
-    case 4 * 8 + 4: return (const void*)k_persistent<4, 4, 256>;
+    case 0 * 8 + 1: return (const void*)k_persistent<0, 1, 256, 3>;
+    case 0 * 8 + 2: return (const void*)k_persistent<0, 2, 256, 3>;
+    case 0 * 8 + 4: return (const void*)k_persistent<0, 4, 256, 3>;
+    case 1 * 8 + 1: return (const void*)k_persistent<1, 1, 256, 3>;
+    case 1 * 8 + 2: return (const void*)k_persistent<1, 2, 256, 3>;
+    case 1 * 8 + 4: return (const void*)k_persistent<1, 4, 256, 3>;
+    case 2 * 8 + 1: return (const void*)k_persistent<2, 1, 256, 3>;
+    case 2 * 8 + 2: return (const void*)k_persistent<2, 2, 256, 3>;
+    case 2 * 8 + 4: return (const void*)k_persistent<2, 4, 256, 3>;
+    case 3 * 8 + 1: return (const void*)k_persistent<3, 1, 256, 3>;
+    case 3 * 8 + 2: return (const void*)k_persistent<3, 2, 256, 3>;
+    case 3 * 8 + 4: return (const void*)k_persistent<3, 4, 256, 3>;
+    case 4 * 8 + 1: return (const void*)k_persistent<4, 1, 256, 3>;
+    case 4 * 8 + 2: return (const void*)k_persistent<4, 2, 256, 3>;
+    case 4 * 8 + 4: return (const void*)k_persistent<4, 4, 256, 3>;
     default: return nullptr;
     }
 }
 
-hipError_t persistent_occupancy(int prec, int R, int* blocks_per_cu) {
+hipError_t persistent_occupancy(int prec, int R, bool wide, int* blocks_per_cu) {
+    if (wide) return wide_available(prec, R) ? occ_one<1, 1, 4>(blocks_per_cu) : hipErrorInvalidValue;
     switch (prec * 8 + R) {
-    case 0 * 8 + 1: return occ_one<0, 1>(blocks_per_cu);
-    case 0 * 8 + 2: return occ_one<0, 2>(blocks_per_cu);
-    case 0 * 8 + 4: return occ_one<0, 4>(blocks_per_cu);
-    case 1 * 8 + 1: return occ_one<1, 1>(blocks_per_cu);
-    case 1 * 8 + 2: return occ_one<1, 2>(blocks_per_cu);
-    case 1 * 8 + 4: return occ_one<1, 4>(blocks_per_cu);
-    case 2 * 8 + 1: return occ_one<2, 1>(blocks_per_cu);
-    case 2 * 8 + 2: return occ_one<2, 2>(blocks_per_cu);
-    case 2 * 8 + 4: return occ_one<2, 4>(blocks_per_cu);
-    case 3 * 8 + 1: return occ_one<3, 1>(blocks_per_cu);
-    case 3 * 8 + 2: return occ_one<3, 2>(blocks_per_cu);
-    case 3 * 8 + 4: return occ_one<3, 4>(blocks_per_cu);
-    case 4 * 8 + 1: return occ_one<4, 1>(blocks_per_cu);
-    case 4 * 8 + 2: return occ_one<4, 2>(blocks_per_cu);
-    case 4 * 8 + 4: return occ_one<4, 4>(blocks_per_cu);
+    case 0 * 8 + 1: return occ_one<0, 1, 3>(blocks_per_cu);
+    case 0 * 8 + 2: return occ_one<0, 2, 3>(blocks_per_cu);
+    case 0 * 8 + 4: return occ_one<0, 4, 3>(blocks_per_cu);
+    case 1 * 8 + 1: return occ_one<1, 1, 3>(blocks_per_cu);
+    case 1 * 8 + 2: return occ_one<1, 2, 3>(blocks_per_cu);
+    case 1 * 8 + 4: return occ_one<1, 4, 3>(blocks_per_cu);
+    case 2 * 8 + 1: return occ_one<2, 1, 3>(blocks_per_cu);
+    case 2 * 8 + 2: return occ_one<2, 2, 3>(blocks_per_cu);
+    case 2 * 8 + 4: return occ_one<2, 4, 3>(blocks_per_cu);
+    case 3 * 8 + 1: return occ_one<3, 1, 3>(blocks_per_cu);
+    case 3 * 8 + 2: return occ_one<3, 2, 3>(blocks_per_cu);
+    case 3 * 8 + 4: return occ_one<3, 4, 3>(blocks_per_cu);
+    case 4 * 8 + 1: return occ_one<4, 1, 3>(blocks_per_cu);
+    case 4 * 8 + 2: return occ_one<4, 2, 3>(blocks_per_cu);
+    case 4 * 8 + 4: return occ_one<4, 4, 3>(blocks_per_cu);
     default: return hipErrorInvalidValue;
     }
 }

@@ -319,8 +319,8 @@ void build_items(const kde_ctx* c, Plan& p, const std::vector<SampleSpec>& ss) {
 // context's blocks per CU on every CU, but no more than half that many items
 // (blocks of a small launch then take two items per stage, and the CUs keep
 // some of their VALU share for the others) and never more than there are items.
-int grid_for(const kde_ctx* c, int64_t work) {
-    const int64_t full = (int64_t)c->cus * std::max(1, c->blocks_per_cu);
+int grid_for(const kde_ctx* c, int64_t work, bool wide) {
+    const int64_t full = (int64_t)c->cus * std::max(1, wide ? c->blocks_per_cu_wide : c->blocks_per_cu);
     const int64_t w = std::max<int64_t>(1, work);
     return (int)std::min(full, std::max(std::min<int64_t>(c->cus, w), w / 2));
 }
@@ -369,7 +369,10 @@ int upload_plan(kde_ctx* c, Plan& p, hipStream_t s) {
     }
     int64_t per_stage[NUM_STAGES] = {0};
     for (const Item& it : p.items) ++per_stage[it.stage];
-    p.grid = grid_for(c, *std::max_element(per_stage, per_stage + NUM_STAGES));
+    int64_t nmax = 0;
+    for (const Desc& d : p.descs) nmax = std::max<int64_t>(nmax, d.n);
+    p.wide = use_wide(c, nmax);
+    p.grid = grid_for(c, *std::max_element(per_stage, per_stage + NUM_STAGES), p.wide);
     return KDE_OK;
 }
 
@@ -415,7 +418,7 @@ int run_plan(kde_ctx* c, Plan& p, hipStream_t s, kde_result* out = nullptr, bool
         LaunchArgs a = args_for(c, p);
         void* kargs[] = {&a};
         hipKernelNodeParams kn{};
-        kn.func = const_cast<void*>(persistent_kernel(c->precision, c->R));
+        kn.func = const_cast<void*>(persistent_kernel(c->precision, c->R, p.wide));
         kn.gridDim = dim3((unsigned)p.grid);
         kn.blockDim = dim3(kBlock);
         kn.sharedMemBytes = 0;
@@ -569,6 +572,8 @@ int finish(kde_ctx* c, Plan& p, hipStream_t s) {
     c->last_states.assign(p.h_states, p.h_states + p.count);
     float ms = -1.0f;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_device_ms = ms;
+    c->last_grid = p.grid;
+    c->last_waves = p.wide ? 4 : 3;
     return KDE_OK;
 }
 
@@ -687,7 +692,12 @@ int kde_ctx_create(kde_ctx** out, const kde_options* opt) {
     HIPCHK(hipEventCreate(&c->ev0));
     HIPCHK(hipEventCreate(&c->ev1));
     int occ = 0;
-    HIPCHK(persistent_occupancy(c->precision, c->R, &occ));
+    HIPCHK(persistent_occupancy(c->precision, c->R, false, &occ));
+    if (o.blocks_per_cu == 0 && tt.bpc == 0 && wide_available(c->precision, c->R)) {
+        int occ4 = 0;
+        HIPCHK(persistent_occupancy(c->precision, c->R, true, &occ4));
+        if (occ4 > occ) c->blocks_per_cu_wide = occ4;
+    }
     {
         // device address of the static scratch of kde_plugin_bandwidth_noalloc
         const int st = noalloc_init(c->device);
@@ -884,6 +894,14 @@ double kde_ctx_last_device_ms(const kde_ctx* c) {
         return -1.0;
     }
     return c->last_device_ms;
+}
+
+int kde_ctx_last_launch(const kde_ctx* c, int32_t* blocks, int32_t* waves_per_simd) {
+    if (!c) return set_err(KDE_EINVAL, "null context");
+    if (c->last_grid == 0) return set_err(KDE_EINVAL, "no synchronous call on this context yet");
+    if (blocks) *blocks = c->last_grid;
+    if (waves_per_simd) *waves_per_simd = c->last_waves;
+    return ok();
 }
 
 static_assert(NUM_STAGES == KDE_NUM_STAGES, "the timeline has one entry per stage");

@@ -237,7 +237,8 @@ extern "C" int kde_plugin_bandwidth_noalloc(kde_ctx* c, const void* x, int64_t n
     a.ticket = p.ticket;
     a.pc = c->pc;
     a.timeout_ticks = wait_ticks(c, g.TI * (g.W + 4));
-    HIPCHK(launch_persistent(c->precision, c->R, grid_for(c, widest), s, a));
+    const bool wide = use_wide(c, n);
+    HIPCHK(launch_persistent(c->precision, c->R, wide, grid_for(c, widest, wide), s, a));
     HIPCHK(launch_results(p.state, p.outmap, 1, dout, s));
     return ok();
 }

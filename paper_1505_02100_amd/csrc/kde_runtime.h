@@ -17,10 +17,13 @@ namespace kde {
 hipError_t launch_init(State* states, Pub* pubs, int32_t count, uint32_t* ticket, hipStream_t s);
 hipError_t launch_results(const State* states, const int32_t* outmap, int64_t n_out, kde_result* out,
                           hipStream_t s);
-hipError_t launch_persistent(int prec, int R, int grid, hipStream_t s, const LaunchArgs& a);
-// The persistent kernel's instantiation for (precision, R), for graph nodes; nullptr if none.
-const void* persistent_kernel(int prec, int R);
-hipError_t persistent_occupancy(int prec, int R, int* blocks_per_cu);
+// The persistent kernel for (precision, R), held to three waves per SIMD, or
+// (wide) to four, which only the default precision at R = 1 has.
+bool wide_available(int prec, int R);
+hipError_t launch_persistent(int prec, int R, bool wide, int grid, hipStream_t s, const LaunchArgs& a);
+// The instantiation itself, for graph nodes; nullptr if none.
+const void* persistent_kernel(int prec, int R, bool wide);
+hipError_t persistent_occupancy(int prec, int R, bool wide, int* blocks_per_cu);
 }  // namespace kde
 
 namespace kde {
@@ -46,6 +49,11 @@ constexpr uint64_t kTimeoutTicks = 20ull * 100000000ull;  // 20 s at the 100 MHz
 // far below any measured one: huge samples, whose items take seconds, are
 // not cut off, and a hang still ends.
 constexpr double kSlowPairsPerS = 2e7;
+// Samples from this size up run on the four-wave kernel when the context
+// chose its own tile configuration (measured on MI355X: -1.2% to -1.8% time
+// at n = 2^18 ... 2^20, equal at 2^17, +0.8% at 2^16 with three blocks per CU
+// and +3% with four).
+constexpr int64_t kWideMinN = (int64_t)1 << 18;
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -82,6 +90,7 @@ struct Plan {
     hipEvent_t ev_reset = nullptr;    // recorded after the reset that follows each replay
     hipStream_t reset_stream = nullptr;  // the stream that reset was issued on
     int grid = 0;
+    bool wide = false;                // launched with the four-wave kernel
     ~Plan() {
         // a replay may still be in flight (asynchronous calls): let it finish
         if (ev_reset) (void)hipEventSynchronize(ev_reset);
@@ -140,6 +149,8 @@ struct kde_ctx {
     int64_t mem_budget = 0;
     int R = 1;
     int blocks_per_cu = 0;
+    int blocks_per_cu_wide = 0;               // > 0: large samples use the four-wave kernel with this many blocks per CU
+    int last_grid = 0, last_waves = 0;        // launch shape of the last synchronous call
     int64_t target_items = 0;                 // 0 = by sample size
     int64_t bucket_target[64] = {0};          // from a tune table: by floor(log2 n)
     int64_t pair_budget = 0;                  // from a tune table: pairs per item for every n
@@ -163,7 +174,9 @@ inline uint64_t wait_ticks(const kde_ctx* c, int64_t max_item_pairs) {
     return kTimeoutTicks + (uint64_t)((double)max_item_pairs / kSlowPairsPerS * 1e8);
 }
 PairGeom pair_geom(const kde_ctx* c, int64_t n);
-int grid_for(const kde_ctx* c, int64_t work);
+int grid_for(const kde_ctx* c, int64_t work, bool wide);
+// Whether a launch whose largest sample has nmax elements takes the four-wave kernel.
+inline bool use_wide(const kde_ctx* c, int64_t nmax) { return c->blocks_per_cu_wide > 0 && nmax >= kWideMinN; }
 // Items of one sample, stage by stage, appended to `out` (slot numbers from
 // slot_base[] of `d`, which must already be filled).  Used by the server.
 void sample_items(const kde_ctx* c, int32_t ds, const Desc& d, const SampleSpec& ss,

@@ -418,7 +418,7 @@ int launch_step(kde_server* s) {
     for (size_t k = 0; k < m; ++k)
         if (listed[k]) widest_item = std::max(widest_item, s->active[k]->geom.TI * (s->active[k]->geom.W + 4));
     a.timeout_ticks = wait_ticks(s->ctx, widest_item);
-    if (launch_persistent(s->ctx->precision, s->ctx->R, step_grid(s->ctx, (int64_t)total), s->stream, a) !=
+    if (launch_persistent(s->ctx->precision, s->ctx->R, false, step_grid(s->ctx, (int64_t)total), s->stream, a) !=
         hipSuccess) {
         (void)hipGetLastError();
         return fail_step(KDE_EDEVICE);

@@ -141,6 +141,7 @@ _sig("kde_options_init", None, ctypes.POINTER(kde_options))
 _sig("kde_ctx_create", ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(kde_options))
 _sig("kde_ctx_destroy", None, _P)
 _sig("kde_ctx_config", ctypes.c_int, _P, _PI32, _PI32, _PI32, _PI32)
+_sig("kde_ctx_last_launch", ctypes.c_int, _P, _PI32, _PI32)
 _sig("kde_psi", _D, ctypes.POINTER(_D), _I64, ctypes.c_int, _D)
 _sig("kde_plugin_bandwidth", _D, ctypes.POINTER(_D), _I64)
 _sig("kde_psi_ex", ctypes.c_int, _P, _P, _I64, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, _P,
@@ -292,6 +293,12 @@ def kde_ctx_create(precision: int = KDE_FP64_PLAIN, device: int = 0, mem_budget:
 
 def kde_ctx_destroy(ctx: int) -> None:
     _lib.kde_ctx_destroy(ctx)
+
+
+def kde_ctx_last_launch(ctx: int) -> dict:
+    b, w = _I32(), _I32()
+    _check(_lib.kde_ctx_last_launch(ctx, ctypes.byref(b), ctypes.byref(w)), "kde_ctx_last_launch")
+    return dict(blocks=b.value, waves_per_simd=w.value)
 
 
 def kde_ctx_config(ctx: int) -> dict:
@@ -574,6 +581,9 @@ class Context:
 
     def config(self):
         return kde_ctx_config(self.handle)
+
+    def last_launch(self):
+        return kde_ctx_last_launch(self.handle)
 
     def last_timeline(self, sample: int = 0):
         return kde_ctx_last_timeline(self.handle, sample)

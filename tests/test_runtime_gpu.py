@@ -153,3 +153,33 @@ def test_wait_limit_fails_the_sample_and_the_launch_ends(kp):
     with kp.Context(kp.KDE_FP32_COMP, wait_limit_us=10_000_000) as c:
         got = c.plugin_bandwidth(x)
     assert want.status == 0 and (got.h, got.psi6, got.psi4) == (want.h, want.psi6, want.psi4)
+
+
+def test_four_wave_kernel_for_large_samples(kp):
+    # with its own tile configuration a context runs samples of 2^18 elements
+    # and more on the kernel held to four waves per SIMD, smaller ones on the
+    # three-wave kernel; the arithmetic is the same, so results are bitwise
+    # those of a context pinned to three blocks per CU (three-wave kernel)
+    import torch
+    big = torch.from_numpy(synth.bimodal((1 << 18) + 5, 31)).cuda()
+    small = torch.from_numpy(synth.bimodal((1 << 17) + 3, 32)).cuda()
+    with kp.Context(kp.KDE_FP32_COMP) as a, kp.Context(kp.KDE_FP32_COMP, blocks_per_cu=3) as b:
+        for x, waves in ((big, 4), (small, 3)):
+            ra = a.plugin_bandwidth(x)
+            la = a.last_launch()
+            rb = b.plugin_bandwidth(x)
+            lb = b.last_launch()
+            assert la["waves_per_simd"] == waves and lb["waves_per_simd"] == 3
+            cus = torch.cuda.get_device_properties(0).multi_processor_count
+            assert 0 < la["blocks"] <= waves * cus and 0 < lb["blocks"] <= 3 * cus
+            assert (ra.h, ra.psi6, ra.psi4, ra.g2) == (rb.h, rb.psi6, rb.psi4, rb.g2)
+        # the no-allocation entry point follows the same rule, bitwise again
+        out = torch.zeros(ctypes.sizeof(kp.kde_result), dtype=torch.uint8, device="cuda")
+        a.plugin_bandwidth_noalloc(big, out)
+        torch.cuda.synchronize()
+        got = kp.batch_results(out, 1)[0]
+        want = b.plugin_bandwidth(big)
+        assert (got.h, got.psi6, got.psi4) == (want.h, want.psi6, want.psi4)
+    with kp.Context(kp.KDE_FP64_PLAIN) as c:
+        c.plugin_bandwidth(big)
+        assert c.last_launch()["waves_per_simd"] == 3
