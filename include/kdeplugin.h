@@ -114,7 +114,10 @@ typedef struct {
     const char* tune_table; /* path of an autotune table written by kde_autotune, or NULL
                                for the built-in tile configuration                          */
     int32_t rows_per_lane;   /* 0 = from the tune table / default; else 1, 2 or 4          */
-    int32_t blocks_per_cu;   /* 0 = from the tune table / occupancy; else 1..16            */
+    int32_t blocks_per_cu;   /* 0 = from the tune table / occupancy (and, with neither
+                                set, samples of 2^18 or more at KDE_FP32_COMP and one row per
+                                lane run on a kernel built for four waves per SIMD, with
+                                four blocks per CU); else 1..16 on the three-wave kernel      */
     int32_t target_items;    /* 0 = default; pair work items per stage for large n         */
     int32_t wait_limit_us;   /* 0 = default; else the longest an in-kernel wait for an
                                 earlier stage may take, in microseconds, before the sample
@@ -419,8 +422,10 @@ KDE_API int kde_server_fail_next_step(kde_server* srv, int32_t code);
 
 /* Search the tile configuration for opt->precision on opt->device (opt may
  * be NULL for the defaults): rows per lane R in {1, 2, 4} (tile height 256 R),
- * persistent blocks per CU (occupancy limit and one below) and the size of
- * the pair items.  Each candidate is timed with HIP events on the launch
+ * persistent blocks per CU (0 = the context's own choice, the occupancy
+ * limit, one below it; table value 0 leaves the choice, including the
+ * four-wave kernel for large samples, to the context) and the size of the
+ * pair items.  Each candidate is timed with HIP events on the launch
  * stream (median of reps launches) on synthetic normal samples with the
  * sizes ns[0..count):
  *   mode KDE_TUNE_SINGLE: every size alone, one selection per launch; the

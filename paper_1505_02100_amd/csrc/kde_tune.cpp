@@ -53,6 +53,15 @@ std::vector<double> normal_sample(int64_t n, uint64_t seed) {
 
 constexpr int kWarmupMs = 300;  // load before the first timed candidate
 
+// Blocks per CU to try: 0 (the context's own choice: the occupancy limit, and
+// the four-wave kernel for large samples where it has one), the occupancy
+// limit, and one below it.  A table with 0 leaves the choice to the context.
+std::vector<int> bpc_candidates(int occ) {
+    std::vector<int> v{0, occ};
+    if (occ > 1) v.push_back(occ - 1);
+    return v;
+}
+
 // Median device time (ms) of `reps` selections on a context, or -1 on error.
 double time_ctx(kde_ctx* c, const void* dx, int64_t n, int reps) {
     kde_result r;
@@ -176,7 +185,7 @@ extern "C" int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t c
             int32_t occ = 1;
             kde_ctx_config(probe, nullptr, nullptr, nullptr, &occ);
             kde_ctx_destroy(probe);
-            for (int bpc = occ; bpc >= std::max(1, occ - 1); --bpc) {
+            for (int bpc : bpc_candidates(occ)) {
                 for (int64_t B : budgets) {
                     // a candidate is a table with this pair budget, read back by kde_ctx_create
                     char path[64];
@@ -231,7 +240,7 @@ extern "C" int kde_autotune(const kde_options* opt, const int64_t* ns, int32_t c
         int32_t occ = 1;
         kde_ctx_config(probe, nullptr, nullptr, nullptr, &occ);
         kde_ctx_destroy(probe);
-        for (int bpc = occ; bpc >= std::max(1, occ - 1); --bpc) {
+        for (int bpc : bpc_candidates(occ)) {
             double total = 0.0;
             std::vector<int64_t> tgt(sizes.size(), 0);
             for (size_t q = 0; q < sizes.size(); ++q) {

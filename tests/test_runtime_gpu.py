@@ -183,3 +183,22 @@ def test_four_wave_kernel_for_large_samples(kp):
     with kp.Context(kp.KDE_FP64_PLAIN) as c:
         c.plugin_bandwidth(big)
         assert c.last_launch()["waves_per_simd"] == 3
+
+
+def test_tune_tables_and_the_four_wave_kernel(kp, tmp_path):
+    # a tune table whose blocks per CU is 0 leaves the choice to the context
+    # (four-wave kernel for large samples); a table that names a count pins
+    # the three-wave kernel; results are bitwise equal either way
+    import json
+    import torch
+    x = torch.from_numpy(synth.bimodal((1 << 18) + 5, 33)).cuda()
+    res = {}
+    for bpc in (0, 3):
+        p = tmp_path / f"t{bpc}.json"
+        p.write_text(json.dumps({"precision": kp.KDE_FP32_COMP, "rows_per_lane": 1, "blocks_per_cu": bpc,
+                                 "targets": [[18, 8192]]}))
+        with kp.Context(kp.KDE_FP32_COMP, tune_table=str(p)) as c:
+            r = c.plugin_bandwidth(x)
+            res[bpc] = (r.h, r.psi6, r.psi4, c.last_launch()["waves_per_simd"])
+    assert res[0][3] == 4 and res[3][3] == 3
+    assert res[0][:3] == res[3][:3]
