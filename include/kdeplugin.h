@@ -115,9 +115,11 @@ typedef struct {
                                for the built-in tile configuration                          */
     int32_t rows_per_lane;   /* 0 = from the tune table / default; else 1, 2 or 4          */
     int32_t blocks_per_cu;   /* 0 = from the tune table / occupancy (and, with neither
-                                set, samples of 2^18 or more at KDE_FP32_COMP and one row per
-                                lane run on a kernel built for four waves per SIMD, with
-                                four blocks per CU); else 1..16 on the three-wave kernel      */
+                                set, launches at KDE_FP32_COMP and one row per lane whose
+                                pair stage holds 2^34 pairs or more -- one sample of about
+                                185 000 or more, or a large batch -- run on a kernel built
+                                for four waves per SIMD, with four blocks per CU); else
+                                1..16 on the three-wave kernel                              */
     int32_t target_items;    /* 0 = default; pair work items per stage for large n         */
     int32_t wait_limit_us;   /* 0 = default; else the longest an in-kernel wait for an
                                 earlier stage may take, in microseconds, before the sample
@@ -169,11 +171,12 @@ KDE_API int kde_ctx_config(const kde_ctx* ctx, int32_t* rows_per_lane, int32_t* 
  * it), measured with HIP events on the caller's stream; -1 if none yet. */
 KDE_API double kde_ctx_last_device_ms(const kde_ctx* ctx);
 
-/* Launch shape of the last synchronous call's persistent kernel on this
- * context: its blocks (256 threads each) and the waves per SIMD the kernel is
- * built for (3, or 4 for the default precision at R = 1 on samples of
- * 2^18 elements or more when the context chose its own tile configuration).
- * KDE_EINVAL if the context has made no synchronous call yet. */
+/* Launch shape of the persistent kernel of the last call on this context
+ * (single or batch): its blocks (256 threads each) and the waves per SIMD the kernel is
+ * built for (3, or 4 for the default precision at R = 1 on launches whose
+ * pair stage holds 2^34 pairs or more, when the context chose its own tile
+ * configuration).
+ * KDE_EINVAL if the context has launched nothing yet. */
 KDE_API int kde_ctx_last_launch(const kde_ctx* ctx, int32_t* blocks, int32_t* waves_per_simd);
 
 /* Device timeline of sample `sample` of the last synchronous call on this

@@ -369,9 +369,9 @@ int upload_plan(kde_ctx* c, Plan& p, hipStream_t s) {
     }
     int64_t per_stage[NUM_STAGES] = {0};
     for (const Item& it : p.items) ++per_stage[it.stage];
-    int64_t nmax = 0;
-    for (const Desc& d : p.descs) nmax = std::max<int64_t>(nmax, d.n);
-    p.wide = use_wide(c, nmax);
+    double stage_pairs = 0.0;
+    for (const Desc& d : p.descs) stage_pairs += 0.5 * (double)d.n * (double)(d.n - 1);
+    p.wide = use_wide(c, stage_pairs);
     p.grid = grid_for(c, *std::max_element(per_stage, per_stage + NUM_STAGES), p.wide);
     return KDE_OK;
 }
@@ -456,6 +456,8 @@ int run_plan(kde_ctx* c, Plan& p, hipStream_t s, kde_result* out = nullptr, bool
     }
     if (timed) HIPCHK(hipEventRecord(c->ev0, s));
     HIPCHK(hipGraphLaunch(p.exec, s));
+    c->last_grid = p.grid;
+    c->last_waves = p.wide ? 4 : 3;
     if (timed) HIPCHK(hipEventRecord(c->ev1, s));
     if (out)
         HIPCHK(launch_results((const State*)p.d_states.p, (const int32_t*)p.d_outmap.p,
@@ -572,8 +574,6 @@ int finish(kde_ctx* c, Plan& p, hipStream_t s) {
     c->last_states.assign(p.h_states, p.h_states + p.count);
     float ms = -1.0f;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_device_ms = ms;
-    c->last_grid = p.grid;
-    c->last_waves = p.wide ? 4 : 3;
     return KDE_OK;
 }
 
@@ -898,7 +898,7 @@ double kde_ctx_last_device_ms(const kde_ctx* c) {
 
 int kde_ctx_last_launch(const kde_ctx* c, int32_t* blocks, int32_t* waves_per_simd) {
     if (!c) return set_err(KDE_EINVAL, "null context");
-    if (c->last_grid == 0) return set_err(KDE_EINVAL, "no synchronous call on this context yet");
+    if (c->last_grid == 0) return set_err(KDE_EINVAL, "nothing launched on this context yet");
     if (blocks) *blocks = c->last_grid;
     if (waves_per_simd) *waves_per_simd = c->last_waves;
     return ok();

@@ -49,11 +49,14 @@ constexpr uint64_t kTimeoutTicks = 20ull * 100000000ull;  // 20 s at the 100 MHz
 // far below any measured one: huge samples, whose items take seconds, are
 // not cut off, and a hang still ends.
 constexpr double kSlowPairsPerS = 2e7;
-// Samples from this size up run on the four-wave kernel when the context
-// chose its own tile configuration (measured on MI355X: -1.2% to -1.8% time
-// at n = 2^18 ... 2^20, equal at 2^17, +0.8% at 2^16 with three blocks per CU
-// and +3% with four).
-constexpr int64_t kWideMinN = (int64_t)1 << 18;
+// Launches whose pair stage holds at least this many pairs (over all their
+// samples) run on the four-wave kernel when the context chose its own tile
+// configuration.  Measured on MI355X against the three-wave kernel: -1.6% at
+// n = 2^20, -1.2% at 2^19, -1.4% at 2^18 (3.4e10 pairs), equal at 2^17
+// (8.6e9), +0.8% at 2^16 with three blocks per CU and +3% with four (2.1e9:
+// the stage ends and the spill code weigh more there), -1.6% for the
+// 512-sample batch (1e11 pairs per stage in one launch).
+constexpr double kWideMinPairs = 17179869184.0;  // 2^34
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -175,8 +178,10 @@ inline uint64_t wait_ticks(const kde_ctx* c, int64_t max_item_pairs) {
 }
 PairGeom pair_geom(const kde_ctx* c, int64_t n);
 int grid_for(const kde_ctx* c, int64_t work, bool wide);
-// Whether a launch whose largest sample has nmax elements takes the four-wave kernel.
-inline bool use_wide(const kde_ctx* c, int64_t nmax) { return c->blocks_per_cu_wide > 0 && nmax >= kWideMinN; }
+// Whether a launch whose pair stage holds stage_pairs pairs takes the four-wave kernel.
+inline bool use_wide(const kde_ctx* c, double stage_pairs) {
+    return c->blocks_per_cu_wide > 0 && stage_pairs >= kWideMinPairs;
+}
 // Items of one sample, stage by stage, appended to `out` (slot numbers from
 // slot_base[] of `d`, which must already be filled).  Used by the server.
 void sample_items(const kde_ctx* c, int32_t ds, const Desc& d, const SampleSpec& ss,

@@ -156,10 +156,11 @@ def test_wait_limit_fails_the_sample_and_the_launch_ends(kp):
 
 
 def test_four_wave_kernel_for_large_samples(kp):
-    # with its own tile configuration a context runs samples of 2^18 elements
-    # and more on the kernel held to four waves per SIMD, smaller ones on the
-    # three-wave kernel; the arithmetic is the same, so results are bitwise
-    # those of a context pinned to three blocks per CU (three-wave kernel)
+    # with its own tile configuration a context runs launches whose pair stage
+    # holds 2^34 pairs or more (n = 2^18 alone, or a batch of smaller samples)
+    # on the kernel held to four waves per SIMD, smaller ones on the three-wave
+    # kernel; the arithmetic is the same, so results are bitwise those of a
+    # context pinned to three blocks per CU (three-wave kernel)
     import torch
     big = torch.from_numpy(synth.bimodal((1 << 18) + 5, 31)).cuda()
     small = torch.from_numpy(synth.bimodal((1 << 17) + 3, 32)).cuda()
@@ -180,6 +181,13 @@ def test_four_wave_kernel_for_large_samples(kp):
         got = kp.batch_results(out, 1)[0]
         want = b.plugin_bandwidth(big)
         assert (got.h, got.psi6, got.psi4) == (want.h, want.psi6, want.psi4)
+        # a batch of samples too small alone, but with 2^34 pairs per stage in all
+        xs = [torch.from_numpy(synth.bimodal(70000, 40 + k)).cuda() for k in range(8)]
+        ga = a.plugin_bandwidth_batch(xs)
+        assert a.last_launch()["waves_per_simd"] == 4
+        gb = b.plugin_bandwidth_batch(xs)
+        assert b.last_launch()["waves_per_simd"] == 3
+        assert [(r.h, r.psi6, r.psi4) for r in ga] == [(r.h, r.psi6, r.psi4) for r in gb]
     with kp.Context(kp.KDE_FP64_PLAIN) as c:
         c.plugin_bandwidth(big)
         assert c.last_launch()["waves_per_simd"] == 3
