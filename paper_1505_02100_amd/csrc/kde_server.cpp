@@ -274,8 +274,9 @@ Item next_item(Request& r) {
 
 // A step's items come from many requests, one pair item per request per
 // turn: one block per item up to the context's full grid.
-int step_grid(const kde_ctx* c, int64_t items) {
-    return (int)std::min<int64_t>((int64_t)c->cus * std::max(1, c->blocks_per_cu), std::max<int64_t>(1, items));
+int step_grid(const kde_ctx* c, int64_t items, bool wide) {
+    const int bpc = wide ? c->blocks_per_cu_wide : c->blocks_per_cu;
+    return (int)std::min<int64_t>((int64_t)c->cus * std::max(1, bpc), std::max<int64_t>(1, items));
 }
 
 int launch_step(kde_server* s) {
@@ -418,7 +419,8 @@ int launch_step(kde_server* s) {
     for (size_t k = 0; k < m; ++k)
         if (listed[k]) widest_item = std::max(widest_item, s->active[k]->geom.TI * (s->active[k]->geom.W + 4));
     a.timeout_ticks = wait_ticks(s->ctx, widest_item);
-    if (launch_persistent(s->ctx->precision, s->ctx->R, false, step_grid(s->ctx, (int64_t)total), s->stream, a) !=
+    const bool wide = use_wide(s->ctx, step_pairs);  // the four-wave kernel for large steps
+    if (launch_persistent(s->ctx->precision, s->ctx->R, wide, step_grid(s->ctx, (int64_t)total, wide), s->stream, a) !=
         hipSuccess) {
         (void)hipGetLastError();
         return fail_step(KDE_EDEVICE);
