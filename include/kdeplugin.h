@@ -172,7 +172,7 @@ KDE_API int kde_ctx_config(const kde_ctx* ctx, int32_t* rows_per_lane, int32_t* 
 KDE_API double kde_ctx_last_device_ms(const kde_ctx* ctx);
 
 /* Launch shape of the persistent kernel of the last call on this context
- * (single or batch): its blocks (256 threads each) and the waves per SIMD the kernel is
+ * (single, batch or no-allocation): its blocks (256 threads each) and the waves per SIMD the kernel is
  * built for (3, or 4 for the default precision at R = 1 on launches whose
  * pair stage holds 2^34 pairs or more, when the context chose its own tile
  * configuration).

@@ -238,7 +238,10 @@ extern "C" int kde_plugin_bandwidth_noalloc(kde_ctx* c, const void* x, int64_t n
     a.pc = c->pc;
     a.timeout_ticks = wait_ticks(c, g.TI * (g.W + 4));
     const bool wide = use_wide(c, 0.5 * (double)n * (double)(n - 1));
-    HIPCHK(launch_persistent(c->precision, c->R, wide, grid_for(c, widest, wide), s, a));
+    const int grid = grid_for(c, widest, wide);
+    HIPCHK(launch_persistent(c->precision, c->R, wide, grid, s, a));
+    c->last_grid = grid;
+    c->last_waves = wide ? 4 : 3;
     HIPCHK(launch_results(p.state, p.outmap, 1, dout, s));
     return ok();
 }

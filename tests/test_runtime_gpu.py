@@ -179,6 +179,7 @@ def test_four_wave_kernel_for_large_samples(kp):
         a.plugin_bandwidth_noalloc(big, out)
         torch.cuda.synchronize()
         got = kp.batch_results(out, 1)[0]
+        assert a.last_launch()["waves_per_simd"] == 4
         want = b.plugin_bandwidth(big)
         assert (got.h, got.psi6, got.psi4) == (want.h, want.psi6, want.psi4)
         # a batch of samples too small alone, but with 2^34 pairs per stage in all
