@@ -255,7 +255,9 @@ KDE_API int kde_plugin_bandwidth_batch(kde_ctx* ctx, const void* const* xs, cons
  *   synchronizes the stream before reading out, and keeps x and out alive
  *   until then.  The result is bitwise what kde_plugin_bandwidth_ex returns
  *   for the same sample on the same context.  kde_ctx_last_device_ms and the
- *   timeline are not updated.
+ *   timeline are not updated.  The persistent kernel is always the
+ *   three-wave build, which uses no scratch (private) memory, so the launch
+ *   never makes the HIP runtime grow its scratch pool.
  *   Scratch: the work list, per-item partial sums, state and ticket live in a
  *   static device array of KDE_NOALLOC_SCRATCH_BYTES (about 13 MiB) that each
  *   GPU the library runs on holds once until the process ends; its address is

@@ -237,11 +237,13 @@ extern "C" int kde_plugin_bandwidth_noalloc(kde_ctx* c, const void* x, int64_t n
     a.ticket = p.ticket;
     a.pc = c->pc;
     a.timeout_ticks = wait_ticks(c, g.TI * (g.W + 4));
-    const bool wide = use_wide(c, 0.5 * (double)n * (double)(n - 1));
-    const int grid = grid_for(c, widest, wide);
-    HIPCHK(launch_persistent(c->precision, c->R, wide, grid, s, a));
+    // always the three-wave kernel: it needs no scratch (private) memory, so
+    // its launch never makes the HIP runtime grow its scratch pool; the
+    // four-wave kernel spills registers (same results, bitwise)
+    const int grid = grid_for(c, widest, false);
+    HIPCHK(launch_persistent(c->precision, c->R, false, grid, s, a));
     c->last_grid = grid;
-    c->last_waves = wide ? 4 : 3;
+    c->last_waves = 3;
     HIPCHK(launch_results(p.state, p.outmap, 1, dout, s));
     return ok();
 }
