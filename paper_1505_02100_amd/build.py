@@ -45,18 +45,51 @@ def torch_hip_libdir() -> str:
     return d
 
 
+# Per-kernel register, scratch and occupancy figures of the device code, as
+# the compiler reports them, written next to the library by build() (tests
+# check the ones the kernels' speed depends on).
+RESOURCES = os.path.join(HERE, "kernel_resources.txt")
+RESOURCE_SOURCES = ("kde_device.hip", "kde_eval.hip")
+
+
+def _resource_lines(stderr: str):
+    """'kernel vgprs scratch occupancy' for every kernel in hipcc's
+    kernel-resource-usage remarks."""
+    out, cur = [], {}
+    for line in stderr.splitlines():
+        if "remark:" not in line:
+            continue
+        text = line.split("remark:", 1)[1].strip()
+        for key, field in (("Function Name:", "name"), ("VGPRs:", "vgprs"),
+                           ("ScratchSize [bytes/lane]:", "scratch"), ("Occupancy [waves/SIMD]:", "occ")):
+            if text.startswith(key):
+                cur[field] = text[len(key):].split("[")[0].strip()
+        if {"name", "vgprs", "scratch", "occ"} <= cur.keys():
+            out.append(f"{cur['name']} {cur['vgprs']} {cur['scratch']} {cur['occ']}")
+            cur = {}
+    return out
+
+
 def build(verbose: bool = False) -> str:
     objs = []
+    resources = []
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", "-c",
                os.path.join(CSRC, src), "-o", obj]
+        if src in RESOURCE_SOURCES:
+            cmd.append("-Rpass-analysis=kernel-resource-usage")
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        if src in RESOURCE_SOURCES:
+            resources += _resource_lines(r.stderr)
         objs.append(obj)
+    with open(RESOURCES, "w") as f:
+        f.write("# kernel vgprs scratch_bytes_per_lane waves_per_simd (gfx950, from hipcc)\n")
+        f.write("\n".join(resources) + "\n")
     tmp = LIB + ".tmp"
     tlib = torch_hip_libdir()
     cmd = ["g++", "-shared", "-fPIC", "-o", tmp, *objs, "-L" + tlib, "-l:libamdhip64.so",
