@@ -264,6 +264,28 @@ void sample_items(const kde_ctx* c, int32_t ds, const Desc& d, const SampleSpec&
         if (s == ST_PSI4) wait = d.mode == MODE_PLUGIN ? ST_PSI6 : ST_SSQ;
         if (s == ST_SUM || s == ST_SSQ) {
             for (int32_t q = 0; q < cnt; ++q) out.push_back(Item{ds, s, wait, q, 0, 0, d.slot_base[s] + q});
+        } else if (d.mode == MODE_PLUGIN && d.n >= kBandMinN) {
+            // large samples: bands of kBandRows row blocks, chunk-major inside
+            // a band (the blocks in flight then share a few column chunks,
+            // which each XCD's L2 holds), the last band row-major (its small
+            // items end the stage)
+            const PairGeom g = pair_geom(c, d.n);
+            int32_t q = 0;
+            for (int64_t b0 = 0; b0 < g.RB; b0 += kBandRows) {
+                const int64_t b1 = std::min<int64_t>(g.RB, b0 + kBandRows);
+                if (b1 == g.RB) {
+                    for (int64_t rb = b0; rb < b1; ++rb)
+                        for (int64_t cb = 0, m = pair_items_in_row(g, rb); cb < m; ++cb)
+                            out.push_back(Item{ds, s, wait, (int32_t)rb, (int32_t)cb, 0, d.slot_base[s] + q++});
+                } else {
+                    int64_t mmax = 0;  // chunks per row change at the width levels
+                    for (int64_t rb = b0; rb < b1; ++rb) mmax = std::max(mmax, pair_items_in_row(g, rb));
+                    for (int64_t cb = 0; cb < mmax; ++cb)
+                        for (int64_t rb = b0; rb < b1; ++rb)
+                            if (cb < pair_items_in_row(g, rb))
+                                out.push_back(Item{ds, s, wait, (int32_t)rb, (int32_t)cb, 0, d.slot_base[s] + q++});
+                }
+            }
         } else {
             const PairGeom g = pair_geom(c, d.n);
             const int64_t first = d.mode == MODE_PLUGIN ? 0 : std::max<int64_t>(0, ss.item_begin);

@@ -18,9 +18,11 @@
 //   k_na_items    writes the work list, one thread per item of each stage;
 //   k_persistent  Steps I-VII, exactly as kde_plugin_bandwidth_ex runs them;
 //   k_results     the kde_result into the caller's device-accessible memory.
-// The work list is the one kde_plugin_bandwidth_ex builds for the same n and
-// context (same items, same order, same slots), so the results are bitwise
-// the same.
+// The work list holds the items kde_plugin_bandwidth_ex lists for the same n
+// and context (the moment items with the same slots), row-block major
+// (kde_plugin_bandwidth_ex orders the pair items of samples of 2^19 or more
+// band-wise instead); each item's partial enters an exact fixed-point sum,
+// so the results are bitwise the same.
 #include <hip/hip_runtime.h>
 
 #include <cstddef>

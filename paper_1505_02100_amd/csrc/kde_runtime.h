@@ -57,6 +57,10 @@ constexpr double kSlowPairsPerS = 2e7;
 // the stage ends and the spill code weigh more there), -1.6% for the
 // 512-sample batch (1e11 pairs per stage in one launch).
 constexpr double kWideMinPairs = 17179869184.0;  // 2^34
+// Pair items of samples this large (FP64 sample of 4 MiB, an XCD's L2) are
+// listed band-wise, chunk-major inside bands of kBandRows row blocks.
+constexpr int64_t kBandMinN = (int64_t)1 << 19;
+constexpr int64_t kBandRows = 512;
 
 // Grow-only device buffer.
 struct DevBuf {
