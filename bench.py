@@ -75,6 +75,24 @@ def stored_oracle_record(workload, x):
     return {k: float.fromhex(v) for k, v in rec["plugin"].items()}
 
 
+def stored_batch_records(xs):
+    """The FP64 oracle's records of the 512-sample batch (tests/golden), in
+    sample order, if present and made from the same bytes; else None."""
+    if not os.path.exists(GOLDEN_FULL):
+        return None
+    with open(GOLDEN_FULL) as f:
+        rec = json.load(f).get("batch512")
+    from paper_1505_02100_amd import synth
+    if not rec or len(rec["samples"]) != len(xs):
+        return None
+    out = []
+    for r, x in zip(rec["samples"], xs):
+        if r["sha256"] != synth.sha256(x):
+            return None
+        out.append({k: float.fromhex(v) for k, v in r["plugin"].items()})
+    return out
+
+
 def run_env():
     """The versions and devices a line was measured with."""
     import platform
@@ -190,6 +208,11 @@ def bench_batch(args):
         c.close()
         return b - a, hs
 
+    recs = stored_batch_records(xs)
+    err = None
+    if recs:
+        err = {k: max(abs(getattr(r, k) - q[k]) / abs(q[k]) for r, q in zip(res, recs)) for k in ("h", "psi6", "psi4")}
+        err["source"] = "stored FP64 oracle records of all 512 samples (tests/golden/full_size_records.json)"
     seq64_s, h64 = sequential(kp.KDE_FP64_PLAIN)
     seq_s, hseq = sequential(prec[args.precision], table)
     worst64 = max(abs(r.h - h) / h for r, h in zip(res, h64))
@@ -212,6 +235,7 @@ def bench_batch(args):
                                      "selections_per_s": round(len(xs) / seq64_s, 1),
                                      "speedup_of_batch": round(seq64_s / per, 2),
                                      "max_rel_diff_h": worst64},
+           "max_rel_err_vs_oracle": err,
            "sequential_same_precision": {"seconds": round(seq_s, 4),
                                          "selections_per_s": round(len(xs) / seq_s, 1),
                                          "speedup_of_batch": round(seq_s / per, 2),

@@ -207,6 +207,15 @@ def test_batch_512(kp, ctxs, batch512):
     for k in (0, 1, 77, 311, 511):
         s = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth(xds[k])
         assert (s.h, s.psi6, s.psi4) == (b32[k].h, b32[k].psi6, b32[k].psi4)
+    # the item sizes the batch autotuner picks on MI355X (pair budgets of 2^21
+    # and 2^22 pairs, the benchmark's launch configuration): every sample
+    # against the oracle again
+    for budget in (1 << 21, 1 << 22):
+        with kp.Context(kp.KDE_FP32_COMP, pair_budget=budget) as c:
+            res = c.plugin_bandwidth_batch(xds)
+        for k in range(len(xs)):
+            _against_record(res[k], recs[k]["plugin"], "FP32_COMP", psi_scale=2.0,
+                            where=f"budget {budget} sample {k} n={xs[k].size}")
 
 
 def test_quarter_billion_samples_tail_items(kp, ctxs):
