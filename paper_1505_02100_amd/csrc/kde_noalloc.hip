@@ -137,7 +137,8 @@ __global__ __launch_bounds__(kPrepThreads) void k_na_prepare(unsigned char* base
 // (Step I's two stages, then Step IV's and Step VI's pair items, row blocks
 // in increasing order, column chunks in increasing order within a row
 // block); every stage of the one sample is a single run, and item k's slot
-// is k, as the context's plans number them.
+// is k (the context's plans list the same items in this order below 2^19
+// samples, band-wise above; pair items use no slot).
 __global__ void k_na_items(unsigned char* base, int32_t nm, int32_t np, int64_t RB) {
     const Parts p = parts(base);
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
