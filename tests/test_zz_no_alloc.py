@@ -120,3 +120,19 @@ def test_noalloc_rejects_before_enqueuing(kp):
         with pytest.raises(kp.KdeError) as e:
             big.plugin_bandwidth_noalloc(xd, _out(kp, False))
         assert e.value.code == kp.KDE_EINVAL and "exceeds" in str(e.value)
+
+
+@pytest.mark.parametrize("prec", ["KDE_FP64_PLAIN", "KDE_FP32_COMP"])
+def test_noalloc_row_major_list_equals_the_banded_one(kp, prec):
+    # n = 2^19 + 12345: the allocating call lists the pair items band-wise
+    # (chunk-major in bands of 512 row blocks, a ragged last band), the
+    # no-allocation call row-block major; the sums are exact, so any item
+    # missing from or repeated in either list would change the bits
+    import torch
+    n = (1 << 19) + 12345
+    xd = torch.from_numpy(synth.draw("t3", n, 13)).cuda()
+    with kp.Context(getattr(kp, prec)) as ctx:
+        got = _noalloc(kp, ctx, xd, False)
+        want = ctx.plugin_bandwidth(xd)
+    for k in FIELDS:
+        assert getattr(got, k) == getattr(want, k), (prec, k)
