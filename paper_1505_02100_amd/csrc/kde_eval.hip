@@ -4,8 +4,9 @@
 // on a grid of points or at the samples themselves.
 //
 // Work decomposition.  The m evaluation points are cut into tiles (256
-// points for FP64, one per thread; 4096 for FP32, 16 consecutive points per
-// thread) and the n samples into chunks of W columns; a block evaluates one
+// points for FP64, one per thread; 4096 for FP32, runs of 32 consecutive
+// points, each run shared by two threads) and the n samples into chunks of W
+// columns; a block evaluates one
 // (tile, chunk) item, streaming its chunk through LDS in tiles of column
 // values read as b128 broadcasts, and writes one partial sum per point.  A
 // second kernel adds a point's partials in a fixed order (so results are
@@ -15,24 +16,26 @@
 // s = sqrt(k) / h, v = x s, and the kernel factor exp(-((y - x)/h)^2 / 2) is
 // 2^(-(v_y - v_x)^2).
 //
-// Evenly spaced runs (grids).  When every thread's 16 points are evenly
-// spaced, v_j = u_ref + j ds (j = -8 .. 7 around the run's reference point),
-// a column's 16 terms come from three exp2: with d = u_ref - v_x,
-//     2^(-(d + j ds)^2) = 2^(-K - j^2 ds^2) * E R^j,
-//     E = 2^(K - d^2),  R = 2^(-2 ds d),
-// R^j by repeated multiplication in both directions (R and 1/R), so a pair
-// costs one multiply and one add (an fma and a multiply) instead of an exp2;
-// the factor 2^(-K - j^2 ds^2) is applied once per point at the end.  d is
+// Evenly spaced runs (grids).  When a tile cuts into evenly spaced runs of
+// 32 points, each run is two sub-runs of 16 with reference points u_0 and
+// u_1 = u_0 + 16 ds, point j of sub-run b at u_b + j ds (j = -8 .. 7), and a
+// column's 32 terms come from four exp2: with d_b = u_b - v_x,
+//     2^(-(d_b + j ds)^2) = 2^(-K - j^2 ds^2 - 32 b j ds^2) * E_b R^j,
+//     E_b = 2^(K - d_b^2),  R = 2^(-2 ds d_0),
+// R^j by repeated multiplication in both directions (R and 1/R, shared by
+// the two sub-runs), so a pair costs one multiply and one add instead of an
+// exp2; the factor 2^(-K - ...) is applied once per point at the end.  d_b is
 // formed in FP64 (exact for the columns that matter whatever the offset of
-// the data) and both exponents are rounded to FP32 once.  The offset K = 24
-// keeps E in FP32's normal range for every column within about 12 scaled
+// the data) and the exponents are rounded to FP32 once.  The offset K = 24
+// keeps E_b in FP32's normal range for every column within about 12 scaled
 // units of the reference, so the terms that it would otherwise flush are
-// below 2^-100 of a nearby sample's; the span of a run is limited to 4
-// scaled units (points at most 8 steps from the reference), which bounds
-// the terms (at most 2^(K + 4)) and the error of R^j.  A thread's FP32 sums
-// take kRunFold columns before they are folded into FP64.  The derivation
-// of the error bound (about 6e-6 relative per point, measured 1e-7) is in
-// the tests of this kernel.
+// below 2^-100 of a nearby sample's; the span of a sub-run is limited to 4
+// scaled units (points at most 8 steps from their reference), which bounds
+// the terms (at most 2^(K + 20)) and the error of R^j.  The two threads of a
+// run take every other group of kRunFold columns; their FP32 sums take
+// kRunFold columns before they are folded into FP64, and the two FP64 sums
+// are added at the end.  The derivation of the error bound (about 6.4e-6
+// relative per point, measured 1e-7) is in the tests of this kernel.
 //
 // Other points (unsorted, uneven, or spaced more widely than 0.3 h) take the
 // per-point path in sub-tiles of 256: for 2^(-(v_y - v_x)^2) =
@@ -71,9 +74,13 @@ constexpr int NGROUP = BLOCK / GROUP;
 constexpr int TJN = 256;        // columns per LDS tile and group (FP32 path; two floats each)
 constexpr int kEvalFold = 4;    // b128 reads per FP32 accumulator before the FP64 fold
 constexpr double kEvalSpan = 8.0;
-constexpr int RUN = 16;              // points per thread in an FP32 tile
-constexpr int RUN_REF = 8;           // the run's reference point
-constexpr int TP32 = BLOCK * RUN;    // points per FP32 tile
+constexpr int RUN = 32;              // points of an evenly spaced run (two threads share one)
+constexpr int SUB = 16;              // points per sub-run (one reference point each)
+constexpr int SUB_REF = 8;           // a sub-run's reference point
+constexpr int RUNS = BLOCK / 2;      // runs per FP32 tile
+constexpr int TP32 = RUNS * RUN;     // points per FP32 tile
+static_assert(RUN == 2 * SUB && TP32 % BLOCK == 0, "run layout");
+static_assert(SUB * RUNS <= NGROUP * TJN, "the exchange of half sums fits the column tile");
 static_assert(TP32 == kTilePoints32 && BLOCK == kTilePoints64, "tile sizes the host assumes");
 static_assert(NGROUP * TJN >= TJ, "the FP64 column tile fits the group tiles");
 constexpr double kRunTol = 1e-9;     // evenly spaced to this many scaled units
@@ -289,62 +296,77 @@ __global__ __launch_bounds__(BLOCK) void k_eval64(EvalArgs a) {
 }
 
 // One step of an evenly spaced run: column v_x (scaled, centred) against the
-// lane's RUN points v_j = u_ref + j ds, j = i - RUN_REF.  With d = u_ref - v_x,
-//     -(d + j ds)^2 = -d^2 - 2 j ds d - j^2 ds^2,
-// so 2^(K - (d + j ds)^2 + j^2 ds^2) = E R^j with E = 2^(K - d^2) and
-// R = 2^(-2 ds d): three exp2 per column, then one multiply and one add per
-// point; the factor 2^(-K - j^2 ds^2) is applied to the point's sum at the
-// end.  Both exponents are formed in FP64 and rounded once; the R exponent is
-// clamped to +-kRunArgMax, which only changes columns whose E is 0.
-__device__ __forceinline__ void run_step(double vx, double u_ref, double m2ds, float (&acc)[RUN]) {
-    const double d = u_ref - vx;
-    const float ea = (float)__builtin_fma(-d, d, kRunK);
-    const float ra = __builtin_amdgcn_fmed3f((float)(d * m2ds), -kRunArgMax, kRunArgMax);
-    const float e = __builtin_amdgcn_exp2f(ea);
-    const float r = __builtin_amdgcn_exp2f(ra);
-    const float ri = __builtin_amdgcn_exp2f(-ra);
-    acc[RUN_REF] += e;
+// run's RUN points, two sub-runs of SUB points with reference points u_b =
+// u_0 + b SUB ds (b = 0, 1); point i of sub-run b sits at u_b + j ds,
+// j = i - SUB_REF.  With d_b = u_b - v_x,
+//     -(d_b + j ds)^2 = -d_b^2 - 2 j ds d_b - j^2 ds^2,
+// and d_b = d_0 + b SUB ds, so with E_b = 2^(K - d_b^2) and one ratio
+// R = 2^(-2 ds d_0) for both sub-runs,
+//     E_b R^j = 2^(K - (d_b + j ds)^2 + j^2 ds^2 + 2 j b SUB ds^2):
+// four exp2 per column (E_0, E_1, R, 1/R), then one multiply and one add per
+// point; the factor 2^(-K - j^2 ds^2 - 2 j b SUB ds^2) is applied to the
+// point's sum at the end.  The exponents are formed in FP64 and rounded once;
+// the R exponent is clamped to +-kRunArgMax, which only changes columns whose
+// E_0 and E_1 are both 0.
+__device__ __forceinline__ void run_chain(float e, float r, float ri, float* acc) {
+    acc[SUB_REF] += e;
     float t = e;
 #pragma unroll
-    for (int j = 1; j < RUN - RUN_REF; ++j) {
+    for (int j = 1; j < SUB - SUB_REF; ++j) {
         t *= r;
-        acc[RUN_REF + j] += t;
+        acc[SUB_REF + j] += t;
     }
     t = e;
 #pragma unroll
-    for (int j = 1; j <= RUN_REF; ++j) {
+    for (int j = 1; j <= SUB_REF; ++j) {
         t *= ri;
-        acc[RUN_REF - j] += t;
+        acc[SUB_REF - j] += t;
     }
 }
 
-// One (tile, chunk) item, FP32: a tile of RUN * 256 points, RUN consecutive
-// points per thread.  If every thread's points are an evenly spaced run (to
-// kRunTol scaled units, spanning at most kRunSpan) the block takes the run
-// path; otherwise it evaluates the tile as RUN sub-tiles of 256 points, one
-// point per thread.
-__global__ __launch_bounds__(BLOCK) void k_eval32(EvalArgs a) {
+__device__ __forceinline__ void run_step(double vx, double u0, double u1, double m2ds, float (&acc)[RUN]) {
+    const double d0 = u0 - vx, d1 = u1 - vx;
+    const float ea0 = (float)__builtin_fma(-d0, d0, kRunK);
+    const float ea1 = (float)__builtin_fma(-d1, d1, kRunK);
+    const float ra = __builtin_amdgcn_fmed3f((float)(d0 * m2ds), -kRunArgMax, kRunArgMax);
+    const float e0 = __builtin_amdgcn_exp2f(ea0);
+    const float e1 = __builtin_amdgcn_exp2f(ea1);
+    const float r = __builtin_amdgcn_exp2f(ra);
+    const float ri = __builtin_amdgcn_exp2f(-ra);
+    run_chain(e0, r, ri, acc);
+    run_chain(e1, r, ri, acc + SUB);
+}
+
+// One (tile, chunk) item, FP32: a tile of TP32 points.  If the tile cuts into
+// evenly spaced runs of RUN consecutive points (each to kRunTol scaled units,
+// a sub-run spanning at most kRunSpan) the block takes the run path: threads
+// t and t + RUNS share run t, each taking every other group of kRunFold
+// columns, and add their sums at the end.  Otherwise it evaluates the tile as
+// sub-tiles of 256 points, one point per thread.
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_eval32(EvalArgs a) {
     __shared__ __align__(16) double tile64[NGROUP * TJN];
     __shared__ double red[2 * BLOCK / 64];
     __shared__ double gcen[NGROUP];
     __shared__ int32_t gwide;
 
     const int tid = threadIdx.x;
+    const int run = tid % RUNS, half = tid / RUNS;  // half is the same across a wave
     const int32_t rt = (int32_t)(blockIdx.x / a.n_cc);
     const int32_t cc = (int32_t)(blockIdx.x % a.n_cc);
     const int64_t kb = (int64_t)rt * TP32;
     const int64_t c0 = (int64_t)cc * a.W;
     const int64_t c1 = min(c0 + a.W, a.n);
 
-    // this thread's points k0 .. k0 + live_n - 1: an evenly spaced run?
-    const int64_t k0 = kb + (int64_t)tid * RUN;
+    // the run's points k0 .. k0 + live_n - 1: evenly spaced?  Each half of
+    // the pair checks its sub-run against the line through the run's ends.
+    const int64_t k0 = kb + (int64_t)run * RUN;
     const int live_n = (int)max((int64_t)0, min((int64_t)RUN, a.m - k0));
     bool ok = true;
     double y0 = 0.0, dy = 0.0;
     if (live_n > 0) {
         y0 = a.y[k0];
         if (live_n > 1) dy = (a.y[k0 + live_n - 1] - y0) / (double)(live_n - 1);
-        for (int i = 0; i < live_n; ++i) {
+        for (int i = half * SUB; i < min(live_n, (half + 1) * SUB); ++i) {
             const double yi = a.y[k0 + i];
             if (!isfinite(yi)) {
                 flag_nonfinite(a.flag);
@@ -353,15 +375,16 @@ __global__ __launch_bounds__(BLOCK) void k_eval32(EvalArgs a) {
                 ok = false;
             }
         }
-        if (!(fabs(dy * a.s) * (double)(RUN - 1) <= kRunSpan)) ok = false;
-        // the reference relative to the block's first point: within kRunRefMax
-        // scaled units its FP64 rounding (and that of the centred columns near
-        // it) stays below 2^-32 units; a grid tile spans at most about 1100
-        const double u_ref = (y0 - a.y[kb]) * a.s + (double)RUN_REF * dy * a.s;
-        if (!(fabs(u_ref) < kRunRefMax)) ok = false;
+        if (!(fabs(dy * a.s) * (double)(SUB - 1) <= kRunSpan)) ok = false;
+        // the references relative to the block's first point: within
+        // kRunRefMax scaled units their FP64 rounding (and that of the centred
+        // columns near them) stays below 2^-32 units; a grid tile spans at
+        // most about 1100
+        const double u0 = (y0 - a.y[kb]) * a.s + (double)SUB_REF * dy * a.s;
+        if (!(fabs(u0) < kRunRefMax && fabs(u0 + (double)SUB * dy * a.s) < kRunRefMax)) ok = false;
     }
     if (!__syncthreads_and(ok)) {
-        for (int sub = 0; sub < RUN; ++sub) {
+        for (int sub = 0; sub < TP32 / BLOCK; ++sub) {
             const int64_t kf = kb + (int64_t)sub * BLOCK;
             if (kf >= a.m) break;  // the same for every thread
             eval_subtile_f32(a, cc, kf, c0, c1, tile64, red, gcen, &gwide);
@@ -372,7 +395,8 @@ __global__ __launch_bounds__(BLOCK) void k_eval32(EvalArgs a) {
     // run path: columns centred on the block's first point, in FP64
     const double cb = a.y[kb];
     const double ds = dy * a.s;
-    const double u_ref = (y0 - cb) * a.s + (double)RUN_REF * ds;
+    const double u0 = (y0 - cb) * a.s + (double)SUB_REF * ds;
+    const double u1 = u0 + (double)SUB * ds;
     const double m2ds = -2.0 * ds;
     double tot[RUN];
 #pragma unroll
@@ -385,38 +409,63 @@ __global__ __launch_bounds__(BLOCK) void k_eval32(EvalArgs a) {
             double v = kRunPad;
             if (e < len) {
                 const double x = load_x(a.x, a.dtype, cj + e);
+                // a finite sample whose scaled distance overflows is as far
+                // away as a pad (an infinite one would make the ratio's
+                // exponent inf * 0 in a run of zero spacing)
                 if (!isfinite(x))
                     flag_nonfinite(a.flag);
                 else
-                    v = (x - cb) * a.s;
+                    v = fmin(fmax((x - cb) * a.s, -kRunPad), kRunPad);
             }
             tile64[e] = v;
         }
         __syncthreads();
         const int groups = (len + kRunFold - 1) / kRunFold;
-        for (int g = 0; g < groups; ++g) {
+        for (int g = half; g < groups; g += 2) {
             float acc[RUN];
 #pragma unroll
             for (int i = 0; i < RUN; ++i) acc[i] = 0.0f;
 #pragma unroll
             for (int q = 0; q < kRunFold / 2; ++q) {
                 const double2 v = t2[g * (kRunFold / 2) + q];
-                run_step(v.x, u_ref, m2ds, acc);
-                run_step(v.y, u_ref, m2ds, acc);
+                run_step(v.x, u0, u1, m2ds, acc);
+                run_step(v.y, u0, u1, m2ds, acc);
             }
 #pragma unroll
             for (int i = 0; i < RUN; ++i) tot[i] += (double)acc[i];
         }
     }
+    // the two halves add their sums through LDS: half 0 finishes sub-run 0,
+    // half 1 sub-run 1 (a + b == b + a, so the result does not depend on
+    // which half adds)
+    double* xch = tile64;
 #pragma unroll
-    for (int i = 0; i < RUN; ++i) {
-        if (i < live_n) {
-            const double j = (double)(i - RUN_REF);
-            const double t = tot[i] * exp2(-(double)kRunK - j * j * ds * ds);
-            if (a.n_cc == 1)
-                a.out[k0 + i] = t * a.norm;
-            else
-                a.part[(int64_t)cc * a.m + k0 + i] = t;
+    for (int b = 0; b < 2; ++b) {
+        __syncthreads();
+        if (half != b) {
+#pragma unroll
+            for (int i = 0; i < SUB; ++i) xch[i * RUNS + run] = tot[b * SUB + i];
+        }
+        __syncthreads();
+        if (half == b) {
+#pragma unroll
+            for (int i = 0; i < SUB; ++i) tot[b * SUB + i] += xch[i * RUNS + run];
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        if (half != b) continue;
+#pragma unroll
+        for (int i = 0; i < SUB; ++i) {
+            const int p = b * SUB + i;
+            if (p < live_n) {
+                const double j = (double)(i - SUB_REF);
+                const double t = tot[p] * exp2(-(double)kRunK - j * j * ds * ds - 2.0 * j * (double)(b * SUB) * ds * ds);
+                if (a.n_cc == 1)
+                    a.out[k0 + p] = t * a.norm;
+                else
+                    a.part[(int64_t)cc * a.m + k0 + p] = t;
+            }
         }
     }
 }

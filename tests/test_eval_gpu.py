@@ -15,14 +15,18 @@ differences in FP64 (only the square's and exp2's rounding, a few u32 times
 d^2).  The sums of positive terms add a few u32.  Points where the density is
 below 1e-30 of its maximum (terms below FP32's range) are not compared.
 
-Evenly spaced runs (16 consecutive points a thread, spacing ds <= 4/15 scaled
-units): with d = u_ref - v_x formed in FP64, point j's term is
-2^(-K - j^2 ds^2) E R^j with E = 2^(fl(K - d^2)), R = 2^(fl(-2 ds d)), K = 24,
-and R^j taken by |j| <= 8 FP32 multiplications.  Over the terms that matter
-(|d + j ds| <= 5, so |d| <= 7.2): ln2 u32 |K - d^2| <= 19 u32 from E's
-exponent, per step ln2 u32 |2 ds d| + 2 u32 (exp2) + u32 (multiply) <= 5.6 u32,
-so 45 u32 over 8 steps, and 31 u32 from FP32 sums of 32 terms: about 97 u32 =
-5.8e-6 in all, below 1e-5.
+Evenly spaced runs (32 consecutive points, two sub-runs of 16 each with its
+own reference point u_b = u_0 + 16 b ds, spacing ds <= 4/15 scaled units):
+with d_b = u_b - v_x formed in FP64, point j of sub-run b has the term
+2^(-K - j^2 ds^2 - 32 b j ds^2) E_b R^j with E_b = 2^(fl(K - d_b^2)),
+R = 2^(fl(-2 ds d_0)) (one ratio for both sub-runs), K = 24, and R^j taken by
+|j| <= 8 FP32 multiplications.  Over the terms that matter
+(|d_b + j ds| <= 5, so |d_b| <= 7.2 and |d_0| <= 7.2 + 16 ds <= 11.5):
+ln2 u32 |K - d_b^2| <= 19 u32 from E's exponent, per step
+ln2 u32 |2 ds d_0| + 2 u32 (exp2) + u32 (multiply) <= 7.2 u32, so 58 u32
+over 8 steps, and 31 u32 from FP32 sums of 32 terms: about 108 u32 = 6.4e-6
+in all, below 1e-5.  The two threads that share a run add their FP64 sums
+(a few u64).
 """
 import math
 
@@ -153,16 +157,19 @@ def _rel(got, ref):
 
 
 def test_evenly_spaced_runs_and_their_fallbacks(kp, ctxs):
-    # FP32 tiles of 4096 points take the run path when every thread's 16
-    # points are evenly spaced and span at most 4 scaled units, and the
-    # per-point path otherwise; every case against the oracle, ragged tails
-    # included
+    # FP32 tiles of 4096 points take the run path when every run of 32
+    # points is evenly spaced and its 16-point sub-runs span at most 4 scaled
+    # units, and the per-point path otherwise; every case against the oracle,
+    # ragged tails included (a last run with 17 live points, with 10, and
+    # with 31)
     c32, c64 = ctxs[kp.KDE_FP32_COMP], ctxs[kp.KDE_FP64_PLAIN]
     x = synth.draw("bimodal", 30000, 31)
     h = 0.05
     lo, hi = x.min() - 1.0, x.max() + 1.0
     cases = {
         "ascending, ragged": np.linspace(lo, hi, 2 * 4096 + 17),
+        "ragged, one live sub-run": np.linspace(lo, hi, 4096 + 10),
+        "ragged, second sub-run partly live": np.linspace(hi, lo, 4096 + 32 + 31),
         "descending": np.linspace(hi, lo, 5000),
         "constant": np.full(40, 0.3),
         "one point": np.array([0.25]),
@@ -179,6 +186,22 @@ def test_evenly_spaced_runs_and_their_fallbacks(kp, ctxs):
         ref = oracle.kde_eval(x, h, y)
         assert _rel(c32.eval(x, y, h), ref) <= FP32_TOL, name
         assert _rel(c64.eval(x, y, h), ref) <= 2 * x.size * U + 4 * U, name
+
+
+def test_runs_with_samples_beyond_the_scaled_range(kp, ctxs):
+    # samples so far out that (x - y) / h overflows FP64 contribute 0, also in
+    # runs of zero spacing (a constant grid, a single point), where the
+    # ratio's exponent would otherwise be inf * 0
+    x = np.concatenate([synth.draw("bimodal", 5000, 3), [1.5e308, -1.5e308]])
+    h = 0.05
+    for y in (np.full(40, 0.3), np.array([0.25]), np.linspace(-3.0, 3.0, 4096 + 40)):
+        ref = oracle.kde_eval(x, h, y)
+        assert np.all(np.isfinite(ref))
+        for p in (kp.KDE_FP32_COMP, kp.KDE_FP64_PLAIN):
+            got = ctxs[p].eval(x, y, h)
+            assert np.all(np.isfinite(got)), p
+            tol = FP32_TOL if p == kp.KDE_FP32_COMP else 2 * x.size * U + 4 * U
+            assert _rel(got, ref) <= tol, p
 
 
 def test_runs_far_from_the_data(kp, ctxs):
@@ -210,7 +233,7 @@ def test_runs_are_deterministic_and_flag_nonfinite_points(kp, ctxs):
 @pytest.mark.parametrize("span", [3.99, 4.01])
 @pytest.mark.parametrize("offset", [0.0, 1e6])
 def test_runs_at_the_span_limit_and_far_from_zero(kp, ctxs, span, offset):
-    # grids whose 16-point runs span just under (run path) and just over
+    # grids whose 16-point sub-runs span just under (run path) and just over
     # (per-point path) 4 scaled units, on data near zero and near 1e6: both
     # paths within the FP32 bound of the oracle
     h = 0.2
