@@ -245,22 +245,27 @@ def bench_batch(args):
 
 
 def bench_eval(args):
-    """Density evaluation (equation (1)) with the selected bandwidth: the
-    n = 2^20 lognormal workload sample on a grid of 4096 points spanning its
-    0.1% to 99.9% quantiles; one step = one evaluation of all 4096 points
-    (n m pair evaluations), sample and grid resident in HBM."""
+    """Density evaluation (equation (1)) with the selected bandwidth.
+    eval4096: the n = 2^20 lognormal workload sample on a grid of 4096
+    points spanning its 0.1% to 99.9% quantiles (evenly spaced runs).
+    eval-samples: the n = 2^18 lognormal sample at its own samples, in the
+    order drawn (unsorted, so the per-point path with FP64 differences).
+    One step = one evaluation of all m points (n m pair evaluations), sample
+    and points resident in HBM."""
     import numpy as np
     import torch
     from paper_1505_02100_amd import kdeplugin as kp
     from paper_1505_02100_amd import synth
     prec = {"fp32": kp.KDE_FP32_COMP, "fp32x": kp.KDE_FP32_COMP_EXACT, "fp32poly": kp.KDE_FP32_POLYEXP,
             "q32": kp.KDE_Q32_32, "fp64": kp.KDE_FP64_PLAIN}
-    x = synth.workload_single_lognormal(1 << 20, 2)
-    n, m = x.size, 4096
+    at_samples = args.workload == "eval-samples"
+    x = synth.workload_single_lognormal(1 << 18 if at_samples else 1 << 20, 2)
+    n = x.size
+    m = n if at_samples else 4096
     xd = torch.from_numpy(x).cuda()
     ctx = kp.Context(prec[args.precision])
     h = ctx.plugin_bandwidth(xd).h
-    y = np.linspace(np.quantile(x, 0.001), np.quantile(x, 0.999), m)
+    y = x.copy() if at_samples else np.linspace(np.quantile(x, 0.001), np.quantile(x, 0.999), m)
     yd = torch.from_numpy(y).cuda()
     for _ in range(max(1, args.warmup)):
         ctx.eval(xd, yd, h)
@@ -281,8 +286,10 @@ def bench_eval(args):
            "warmup": args.warmup, "ms_per_step": round(per * 1e3, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
-           "config": {"workload": "density evaluation f(y; h) on a 4096-point grid for the n=2^20 "
-                                  "lognormal sample (1e3*exp(Z)-5e2, seed 2) with its selected h",
+           "config": {"workload": ("density evaluation f(x_k; h) at the n=2^18 lognormal sample's own "
+                                   "points, unsorted (1e3*exp(Z)-5e2, seed 2), with its selected h" if at_samples else
+                                   "density evaluation f(y; h) on a 4096-point grid for the n=2^20 "
+                                   "lognormal sample (1e3*exp(Z)-5e2, seed 2) with its selected h"),
                       "n": n, "m": m, "h": h, "precision": args.precision},
            "device_ms": {q: round(float(np.percentile(dev, p)), 4) for q, p in (("p10", 10), ("p50", 50), ("p90", 90))},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
@@ -300,7 +307,7 @@ def bench_eval(args):
         got = f.cpu().numpy()[pick]
         out["cpu_baseline"] = {"value": n * k / (b - a), "unit": "pair-evals/s", "cores": oracle.num_threads(),
                                "kind": "oracle",
-                               "sample": f"{k} of the {m} grid points against all n samples ({b - a:.2f} s)"}
+                               "sample": f"{k} of the {m} points against all n samples ({b - a:.2f} s)"}
         out["max_rel_err_vs_oracle"] = float(np.max(np.abs(got - ref) / ref))
     ctx.close()
     print(json.dumps(out))
@@ -411,7 +418,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["fp32", "fp32x", "fp32poly", "q32", "fp64"], default="fp32")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch512", "serve", "eval4096", "issue-rate"],
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch512", "serve", "eval4096", "eval-samples",
+                                                               "issue-rate"],
                     default="lognormal1m")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window in seconds")
@@ -451,7 +459,7 @@ def main():
     if args.workload == "serve":
         bench_serve(args)
         return
-    if args.workload == "eval4096":
+    if args.workload in ("eval4096", "eval-samples"):
         bench_eval(args)
         return
     if args.workload == "issue-rate":

@@ -9,7 +9,7 @@ namespace kde {
 namespace eval {
 
 // Points per tile: one per thread (FP64 plain); 4096 (FP32), runs of 32 points
-// shared by two threads, or 16 sub-tiles of 256 points one per thread.
+// shared by two threads, or 8 sub-tiles of 512 points, two per thread.
 constexpr int kTilePoints64 = 256;
 constexpr int kTilePoints32 = 4096;
 

@@ -38,16 +38,17 @@
 // relative per point, measured 1e-7) is in the tests of this kernel.
 //
 // Other points (unsorted, uneven, or spaced more widely than 0.3 h) take the
-// per-point path in sub-tiles of 256: for 2^(-(v_y - v_x)^2) =
+// per-point path in sub-tiles of 512, two adjacent points per thread (each
+// column read from LDS serves both): for 2^(-(v_y - v_x)^2) =
 // 2^(-v_y^2) 2^(v_x (2 v_y) - v_x^2), with (v_x, -v_x^2) stored per column a
 // pair costs one fma, one v_exp_f32 and an add, and each point's sum is
 // scaled by 2^(-v_y^2) once.  The exponent v_y^2 - (v_y - v_x)^2 never
 // exceeds v_y^2, so nothing overflows, and far columns underflow to 0 as
-// they should.  Each group of 32 points (half a wave) has its own centre c,
-// the midrange of its points, and its own FP32 copy of the column tile in
-// LDS, centred on it: the rounding of v_y and of the columns that matter
-// (within a few bandwidths of the group) then stays at a few ulp of small
-// numbers.  A sub-tile with a group whose points spread over more than
+// they should.  Each group of 32 lanes (64 points, half a wave) has its own
+// centre c, the midrange of its points, and its own FP32 copy of the column
+// tile in LDS, centred on it: the rounding of v_y and of the columns that
+// matter (within a few bandwidths of the group) then stays at a few ulp of
+// small numbers.  A sub-tile with a group whose points spread over more than
 // kEvalSpan scaled units (about 9.4 h) takes the difference y - x in FP64
 // instead (then squares it in FP64 and rounds once before the exp2); this
 // is the case for unsorted evaluation points.  Each point keeps four FP32
@@ -74,12 +75,14 @@ constexpr int NGROUP = BLOCK / GROUP;
 constexpr int TJN = 256;        // columns per LDS tile and group (FP32 path; two floats each)
 constexpr int kEvalFold = 4;    // b128 reads per FP32 accumulator before the FP64 fold
 constexpr double kEvalSpan = 8.0;
+constexpr int PPT = 2;               // points per thread on the per-point path (FP32)
+constexpr int SUBTILE = BLOCK * PPT; // points per sub-tile of that path
 constexpr int RUN = 32;              // points of an evenly spaced run (two threads share one)
 constexpr int SUB = 16;              // points per sub-run (one reference point each)
 constexpr int SUB_REF = 8;           // a sub-run's reference point
 constexpr int RUNS = BLOCK / 2;      // runs per FP32 tile
 constexpr int TP32 = RUNS * RUN;     // points per FP32 tile
-static_assert(RUN == 2 * SUB && TP32 % BLOCK == 0, "run layout");
+static_assert(RUN == 2 * SUB && TP32 % SUBTILE == 0, "run layout");
 static_assert(SUB * RUNS <= NGROUP * TJN, "the exchange of half sums fits the column tile");
 static_assert(TP32 == kTilePoints32 && BLOCK == kTilePoints64, "tile sizes the host assumes");
 static_assert(NGROUP * TJN >= TJ, "the FP64 column tile fits the group tiles");
@@ -122,23 +125,34 @@ __device__ __forceinline__ void flag_nonfinite(int32_t* flag) {
     __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// FP32, one 256-point sub-tile of an item whose points are not evenly spaced
-// runs: point k_first + tid against columns [c0, c1), centred per group of 32
-// points (narrow groups) or with FP64 differences (wide blocks).
+// FP32, one sub-tile of SUBTILE points of an item whose points are not
+// evenly spaced runs: points k_first + PPT tid + p (p < PPT, adjacent points
+// in a lane) against columns [c0, c1), centred per group of 32 lanes (narrow
+// groups) or with FP64 differences (wide blocks).  Each column read from LDS
+// serves the lane's PPT points.
 __device__ void eval_subtile_f32(const EvalArgs& a, int32_t cc, int64_t k_first, int64_t c0, int64_t c1,
                                  double* tile64, double* red, double* gcen, int32_t* gwide) {
     const int tid = threadIdx.x;
-    const int64_t k = k_first + tid;
-    const bool live = k < a.m;
-    double y = live ? a.y[k] : 0.0;
-    if (live && !isfinite(y)) {
-        flag_nonfinite(a.flag);
-        y = 0.0;
+    const int64_t kt = k_first + (int64_t)PPT * tid;
+    double y[PPT], tot[PPT];
+    bool live[PPT];
+    double glo = INFINITY, ghi = -INFINITY;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        live[p] = kt + p < a.m;
+        y[p] = live[p] ? a.y[kt + p] : 0.0;
+        if (live[p] && !isfinite(y[p])) {
+            flag_nonfinite(a.flag);
+            y[p] = 0.0;
+        }
+        tot[p] = 0.0;
+        if (live[p]) {
+            glo = fmin(glo, y[p]);
+            ghi = fmax(ghi, y[p]);
+        }
     }
-    double tot = 0.0;
-    // centre and spread of each group of 32 points (lanes 0-31 and 32-63
-    // of a wave); a group without live points is narrow
-    double glo = live ? y : INFINITY, ghi = live ? y : -INFINITY;
+    // centre and spread of each group of 32 lanes (lanes 0-31 and 32-63 of
+    // a wave); a group without live points is narrow
 #pragma unroll
     for (int off = GROUP / 2; off > 0; off >>= 1) {
         glo = fmin(glo, __shfl_xor(glo, off, 64));
@@ -155,14 +169,18 @@ __device__ void eval_subtile_f32(const EvalArgs& a, int32_t cc, int64_t k_first,
     }
     __syncthreads();
     const bool narrow = *gwide == 0;
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (narrow) {
         // 2^(-(v_y - v_x)^2) = 2^(-v_y^2) 2^(fma(v_x, 2 v_y, -v_x^2)): the
         // column tile holds (v_x, -v_x^2), the argument is at most v_y^2
         // (<= 16 here), and the point's factor 2^(-v_y^2) is applied once
         // at the end in FP64, so a pair costs an fma, the exp2 and an add
-        const float vy = (float)((y - gcen[grp]) * a.s);
-        const float vy2 = 2.0f * vy;
+        float vy[PPT], vy2[PPT], acc[PPT][4];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            vy[p] = (float)((y[p] - gcen[grp]) * a.s);
+            vy2[p] = 2.0f * vy[p];
+            acc[p][0] = acc[p][1] = acc[p][2] = acc[p][3] = 0.0f;
+        }
         float2* tile2 = reinterpret_cast<float2*>(tile64);
         const float4* t4 = reinterpret_cast<const float4*>(tile2 + grp * TJN);
         for (int64_t cj = c0; cj < c1; cj += TJN) {
@@ -193,20 +211,33 @@ __device__ void eval_subtile_f32(const EvalArgs& a, int32_t cc, int64_t k_first,
 #pragma unroll
                 for (int q = 0; q < 2 * kEvalFold; ++q) {
                     const float4 v = t4[g * 2 * kEvalFold + q];
-                    acc[(2 * q) & 3] += __builtin_amdgcn_exp2f(__builtin_fmaf(v.x, vy2, v.y));
-                    acc[(2 * q + 1) & 3] += __builtin_amdgcn_exp2f(__builtin_fmaf(v.z, vy2, v.w));
+#pragma unroll
+                    for (int p = 0; p < PPT; ++p) {
+                        acc[p][(2 * q) & 3] += __builtin_amdgcn_exp2f(__builtin_fmaf(v.x, vy2[p], v.y));
+                        acc[p][(2 * q + 1) & 3] += __builtin_amdgcn_exp2f(__builtin_fmaf(v.z, vy2[p], v.w));
+                    }
                 }
-                tot += (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
-                acc[0] = acc[1] = acc[2] = acc[3] = 0.0f;
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    tot[p] += (double)((acc[p][0] + acc[p][1]) + (acc[p][2] + acc[p][3]));
+                    acc[p][0] = acc[p][1] = acc[p][2] = acc[p][3] = 0.0f;
+                }
             }
         }
-        tot *= exp2(-((double)vy * (double)vy));
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) tot[p] *= exp2(-((double)vy[p] * (double)vy[p]));
     } else {
         // one centre for the block, differences in FP64
         double hi;
-        const double lo = block_min_max(live ? y : INFINITY, live ? y : -INFINITY, red, &hi);
+        const double lo = block_min_max(glo, ghi, red, &hi);
         const double c = 0.5 * lo + 0.5 * hi;
-        const double uy = (y - c) * a.s;
+        double uy[PPT];
+        float acc[PPT][4];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            uy[p] = (y[p] - c) * a.s;
+            acc[p][0] = acc[p][1] = acc[p][2] = acc[p][3] = 0.0f;
+        }
         for (int64_t cj = c0; cj < c1; cj += TJ) {
             const int len = (int)min((int64_t)TJ, c1 - cj);
             __syncthreads();
@@ -230,20 +261,29 @@ __device__ void eval_subtile_f32(const EvalArgs& a, int32_t cc, int64_t k_first,
 #pragma unroll
                 for (int q = 0; q < 2 * kEvalFold; ++q) {
                     const double2 v = t2[g * 2 * kEvalFold + q];
-                    const double d0 = uy - v.x, d1 = uy - v.y;
-                    acc[(2 * q) & 3] += __builtin_amdgcn_exp2f(-(float)(d0 * d0));
-                    acc[(2 * q + 1) & 3] += __builtin_amdgcn_exp2f(-(float)(d1 * d1));
+#pragma unroll
+                    for (int p = 0; p < PPT; ++p) {
+                        const double d0 = uy[p] - v.x, d1 = uy[p] - v.y;
+                        acc[p][(2 * q) & 3] += __builtin_amdgcn_exp2f(-(float)(d0 * d0));
+                        acc[p][(2 * q + 1) & 3] += __builtin_amdgcn_exp2f(-(float)(d1 * d1));
+                    }
                 }
-                tot += (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
-                acc[0] = acc[1] = acc[2] = acc[3] = 0.0f;
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    tot[p] += (double)((acc[p][0] + acc[p][1]) + (acc[p][2] + acc[p][3]));
+                    acc[p][0] = acc[p][1] = acc[p][2] = acc[p][3] = 0.0f;
+                }
             }
         }
     }
-    if (live) {
-        if (a.n_cc == 1)
-            a.out[k] = tot * a.norm;
-        else
-            a.part[(int64_t)cc * a.m + k] = tot;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        if (live[p]) {
+            if (a.n_cc == 1)
+                a.out[kt + p] = tot[p] * a.norm;
+            else
+                a.part[(int64_t)cc * a.m + kt + p] = tot[p];
+        }
     }
 }
 
@@ -342,7 +382,7 @@ __device__ __forceinline__ void run_step(double vx, double u0, double u1, double
 // a sub-run spanning at most kRunSpan) the block takes the run path: threads
 // t and t + RUNS share run t, each taking every other group of kRunFold
 // columns, and add their sums at the end.  Otherwise it evaluates the tile as
-// sub-tiles of 256 points, one point per thread.
+// sub-tiles of SUBTILE points, PPT adjacent points per thread.
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_eval32(EvalArgs a) {
     __shared__ __align__(16) double tile64[NGROUP * TJN];
     __shared__ double red[2 * BLOCK / 64];
@@ -384,8 +424,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         if (!(fabs(u0) < kRunRefMax && fabs(u0 + (double)SUB * dy * a.s) < kRunRefMax)) ok = false;
     }
     if (!__syncthreads_and(ok)) {
-        for (int sub = 0; sub < TP32 / BLOCK; ++sub) {
-            const int64_t kf = kb + (int64_t)sub * BLOCK;
+        for (int sub = 0; sub < TP32 / SUBTILE; ++sub) {
+            const int64_t kf = kb + (int64_t)sub * SUBTILE;
             if (kf >= a.m) break;  // the same for every thread
             eval_subtile_f32(a, cc, kf, c0, c1, tile64, red, gcen, &gwide);
         }
