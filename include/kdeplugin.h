@@ -314,11 +314,11 @@ KDE_API int kde_psi_range(kde_ctx* ctx, const void* x, int64_t n, int r, double 
  *     are both host memory (y_mem_kind = KDE_MEM_HOST) or both device memory
  *     on the context's GPU (KDE_MEM_DEVICE).
  *   Precision from the context: KDE_FP64_PLAIN evaluates the definition in
- *     FP64.  The FP32 precisions take 16 consecutive points per thread: where
+ *     FP64.  The FP32 precisions take runs of 32 consecutive points: where
  *     they are evenly spaced (a grid with spacing up to about 0.3 h), a
- *     sample's 16 terms come from three exp2 and a geometric recurrence in
+ *     sample's 32 terms come from four exp2 and a geometric recurrence in
  *     FP32 (exponents formed in FP64), otherwise each term takes one exp2 of
- *     an FP32 exponent (centred per group of 32 points; groups spread over
+ *     an FP32 exponent (centred per group of 64 points; groups spread over
  *     more than about 9 h take the differences in FP64); short FP32 sums are
  *     added in FP64: relative error per point below 1e-5.  Results are
  *     deterministic.
