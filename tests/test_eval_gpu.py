@@ -125,6 +125,23 @@ def test_full_size_lognormal_grid_sampled(kp, ctxs):
     assert np.max(np.abs(got32[idx] - ref) / ref) <= FP32_TOL
 
 
+def test_full_size_at_the_samples_sampled(kp, ctxs):
+    # n = 2^18 workload sample evaluated at its own points in the order drawn
+    # (unsorted: the per-point path with FP64 differences), its selected h:
+    # sampled points, ragged ends of sub-tiles included, against the oracle
+    import torch
+    x = synth.workload_single_lognormal(1 << 18, 2)
+    xd = torch.from_numpy(x).cuda()
+    h = ctxs[kp.KDE_FP32_COMP].plugin_bandwidth(xd).h
+    got32 = ctxs[kp.KDE_FP32_COMP].eval(xd, xd, h).cpu().numpy()
+    got64 = ctxs[kp.KDE_FP64_PLAIN].eval(xd, xd, h).cpu().numpy()
+    idx = np.unique(np.concatenate([[0, 1, 511, 512, 4095, 4096, x.size - 1],
+                                    np.random.default_rng(6).integers(0, x.size, 9)]))
+    ref = oracle.kde_eval(x, h, x[idx])
+    assert np.max(np.abs(got64[idx] - ref) / ref) <= 2 * x.size * U
+    assert np.max(np.abs(got32[idx] - ref) / ref) <= FP32_TOL
+
+
 def test_errors_and_empty(kp, ctxs):
     c = ctxs[kp.KDE_FP32_COMP]
     x = synth.normal(100, 1)
