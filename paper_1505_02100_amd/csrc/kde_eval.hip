@@ -6,9 +6,9 @@
 // Work decomposition.  The m evaluation points are cut into tiles (256
 // points for FP64, one per thread; 4096 for FP32, runs of 32 consecutive
 // points, each run shared by two threads) and the n samples into chunks of W
-// columns; a block evaluates one
-// (tile, chunk) item, streaming its chunk through LDS in tiles of column
-// values read as b128 broadcasts, and writes one partial sum per point.  A
+// columns; a block evaluates one (tile, chunk) item, streaming its chunk
+// through LDS in tiles of column values read as b128 broadcasts, and writes
+// one partial sum per point.  A
 // second kernel adds a point's partials in a fixed order (so results are
 // deterministic) and applies the normalisation 1 / (n h sqrt(2 pi)).
 //
@@ -70,7 +70,7 @@ namespace eval {
 
 constexpr int BLOCK = 256;
 constexpr int TJ = 1024;        // column values per LDS tile (FP64 paths)
-constexpr int GROUP = 32;       // points sharing a centre (FP32 path)
+constexpr int GROUP = 32;       // lanes sharing a centre (FP32 per-point path)
 constexpr int NGROUP = BLOCK / GROUP;
 constexpr int TJN = 256;        // columns per LDS tile and group (FP32 path; two floats each)
 constexpr int kEvalFold = 4;    // b128 reads per FP32 accumulator before the FP64 fold
@@ -87,7 +87,7 @@ static_assert(SUB * RUNS <= NGROUP * TJN, "the exchange of half sums fits the co
 static_assert(TP32 == kTilePoints32 && BLOCK == kTilePoints64, "tile sizes the host assumes");
 static_assert(NGROUP * TJN >= TJ, "the FP64 column tile fits the group tiles");
 constexpr double kRunTol = 1e-9;     // evenly spaced to this many scaled units
-constexpr double kRunSpan = 4.0;     // largest span of a run, scaled units
+constexpr double kRunSpan = 4.0;     // largest span of a sub-run, scaled units
 constexpr double kRunK = 24.0;       // exponent offset of the run terms
 constexpr float kRunArgMax = 60.0f;  // clamp of the ratio's exponent
 constexpr double kRunPad = 1e30;     // column value of a padded (or non-finite) sample
