@@ -226,7 +226,7 @@ def bench_batch(args):
                                   "with equal probability, one persistent launch per batch (graph replay)",
                       "samples": len(xs), "sum_n": int(sum(x.size for x in xs)),
                       "pairs_per_batch": int(pairs), "precision": args.precision,
-                      "tile": ctx.config(), "tune_table": tuned},
+                      "tile": ctx.config(), "launch": ctx.last_launch(), "tune_table": tuned},
            "selections_per_s": round(len(xs) / per, 1),
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
