@@ -134,6 +134,11 @@ def serve_trace(ctx: "kp.Context", trace, duration_s: float, mem_budget: int = 8
     time.monotonic() share the host's monotonic clock).  With drain, the loop
     goes on after the window until every arrived request has finished.
 
+    The backlog at the end gives the pair evaluations still owed to
+    unfinished requests and the time the device would take to drain them at
+    the rate it ran during the loop (a full drain at a heavy overload runs for
+    many minutes).
+
     Reported over ALL arrivals, not only the completed ones: a request still
     unfinished when the loop stops counts at its elapsed time (a lower bound
     on its latency), so the percentiles are lower bounds whenever that many
@@ -204,6 +209,12 @@ def serve_trace(ctx: "kp.Context", trace, duration_s: float, mem_budget: int = 8
     lat_open = [end_ms - (t0 + a[0]) * 1e3 for a in unfinished]
     lat_all = lat_done + lat_open
     served = sum(c.n * (c.n - 1) for c in done if c.status == 0)
+    # pair evaluations still owed at the end: the unfinished requests' totals
+    # less the partial work the device already issued for them
+    owed = sum(a[1] * (a[1] - 1) for a in unfinished)
+    partial = max(0.0, issued - sum(c.n * (c.n - 1) for c in done))
+    remaining = max(0.0, owed - partial)
+    issued_rate = issued / window if window > 0 else 0.0
 
     def pct(v):
         return {"p50": percentile(v, 50), "p99": percentile(v, 99), "max": max(v) if v else math.nan}
@@ -238,5 +249,6 @@ def serve_trace(ctx: "kp.Context", trace, duration_s: float, mem_budget: int = 8
             "failed": sum(1 for c in done if c.status != 0),
             "failed_steps": failed_steps,
             "backlog": {"waiting": len(waiting), "active": len(meta) - stats.queued, "queued": stats.queued,
-                        "not_arrived": len(pending)},
+                        "not_arrived": len(pending), "remaining_pair_evals": remaining,
+                        "drain_s_at_device_rate": remaining / issued_rate if issued_rate > 0 else math.nan},
             "samples": samples}

@@ -110,13 +110,30 @@ def test_serve_trace_small(kp, ctx):
     assert len(rep["completions"]) == len(trace) == rep["arrived"]
     assert rep["unfinished"] == 0 and rep["failed"] == 0
     assert rep["latency_ms"]["p50"] > 0 and rep["latency_ms"]["p99"] >= rep["latency_ms"]["p50"]
-    # drained: the all-arrivals figures are the completed ones, uncensored
+    # drained: the all-arrivals figures are the completed ones, uncensored,
+    # and nothing is owed
     assert rep["latency_ms_all_arrivals"]["p99"] == rep["latency_ms"]["p99"]
     assert not rep["latency_ms_all_arrivals"]["p99_is_lower_bound"]
+    assert rep["backlog"]["remaining_pair_evals"] == 0
     for c in rep["completions"][:12]:
         x = rep["samples"][c.id].cpu().numpy()
         ref = oracle.plugin(x)
         assert c.status == 0 and abs(c.h - ref.h) / ref.h < 1e-6
+
+
+def test_serve_trace_backlog_when_overloaded(kp, ctx):
+    # about 30 requests of 1e12-4e12 pair evaluations each arrive within 1 s,
+    # far more than one GPU serves in that time: the window ends with work
+    # owed, which is reported with the time the device would need to drain it
+    from paper_1505_02100_amd.server import serve_trace
+    trace = synth.serving_trace(rate=30.0, duration=1.0, master=12, n_lo=1e6, n_hi=2e6)
+    rep = serve_trace(ctx, trace, duration_s=1.0)
+    b = rep["backlog"]
+    offered = sum(n * (n - 1) for _, n, _, _ in trace)
+    assert rep["unfinished"] > 0
+    assert 0 < b["remaining_pair_evals"] <= offered
+    assert b["drain_s_at_device_rate"] > 0 and math.isfinite(b["drain_s_at_device_rate"])
+    assert rep["device_pair_evals_per_s"] > 0
 
 
 def test_failed_step_errors_only_its_requests(kp, ctx):
