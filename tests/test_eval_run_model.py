@@ -24,7 +24,8 @@ ARG_MAX = np.float32(60.0)
 
 def run_terms(vx, u0, ds):
     """Per column vx (FP64 array): the 32 point terms E_b R^j in FP32 as the
-    kernel forms them, and the exact factor each one must be multiplied by."""
+    kernel forms them (row p = point p of the run); each point's factor
+    2^(-K - j^2 ds^2 - 2 j b SUB ds^2) is applied by the caller."""
     u1 = u0 + SUB * ds
     d0 = u0 - vx
     d1 = u1 - vx
