@@ -1,5 +1,6 @@
-"""The density evaluation's evenly spaced run terms, replayed in FP32 on the
-CPU against the exact Gaussian factor (no GPU).
+"""The density evaluation's FP32 terms (evenly spaced runs, and the
+per-point path on narrow groups), replayed in FP32 on the CPU against the
+exact Gaussian factor (no GPU).
 
 The GPU kernel forms each column's terms for a run of 32 evenly spaced
 points from four exp2 (two sub-runs of 16 sharing one ratio R) and FP32
@@ -89,3 +90,41 @@ def test_far_columns_contribute_nothing_or_their_value():
         assert np.all(np.isfinite(terms))
         exact_max = np.exp2(-(np.minimum(np.abs(vx), np.abs(vx - 31 * ds)) - 0.0) ** 2)
         assert np.all((terms == 0) | (exact_max > 2.0 ** -130))
+
+
+def fma32(a, b, c):
+    """FP32 fused multiply-add: the product of two FP32 values is exact in
+    FP64, the sum is rounded once more to FP32 (the FP64 rounding in between
+    is far below FP32's)."""
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(np.float32)
+
+
+@pytest.mark.parametrize("c", [0.0, 3.3, -1234.5, 1e6])
+def test_point_terms_within_the_derived_bound(c):
+    # the per-point path on a narrow group: centred scaled values rounded to
+    # FP32 (|v_y| <= 4), columns stored as (v_x, -fl(v_x^2)), the term
+    # 2^(fma(v_x, 2 v_y, -v_x^2)) scaled by 2^(-v_y^2) in FP64; each term that
+    # matters (|d| <= 5) within ln2 |delta a| + 2 ln2 |d| |delta d| + u32, the
+    # bound the GPU tests' tolerance is derived from
+    rng = np.random.default_rng(11)
+    s = 0.85
+    y = c + rng.uniform(-4.0, 4.0, 64) / s
+    x = c + rng.uniform(-9.5, 9.5, 6000) / s
+    vy = ((y - c) * s).astype(np.float32)
+    vx = ((x - c) * s).astype(np.float32)
+    mvx2 = (-(vx * vx)).astype(np.float32)
+    worst = 0.0
+    for k in range(y.size):
+        a = fma32(vx, np.float32(2.0) * vy[k], mvx2)
+        got = np.exp2(a.astype(np.float32)).astype(np.float64) * np.exp2(-float(vy[k]) ** 2)
+        d = (y[k] - x) * s
+        exact = np.exp2(-d * d)
+        keep = np.abs(d) <= 5.0
+        rel = np.abs(got[keep] - exact[keep]) / exact[keep]
+        va, vxa = np.abs(a[keep]).astype(np.float64), vx[keep].astype(np.float64)
+        bound = (np.log(2) * (vxa * vxa + va) + 2 * np.log(2) * np.abs(d[keep]) * (abs(float(vy[k])) + np.abs(vxa))
+                 + 1.0) * U32 + 2 * U32
+        assert np.all(rel <= bound), (k, float(rel.max()))
+        worst = max(worst, float(rel.max()))
+    # the derivation's figure over the terms that matter: 4.4e-6 + 5.4e-6 + 1e-7
+    assert worst <= 1e-5, worst
